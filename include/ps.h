@@ -1,0 +1,160 @@
+/*
+ * ps.h - C ABI of the recycled pseudospectra library for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The library evaluates sigma_min(C - z I) at every point z of a Cartesian
+ * grid, for a complex matrix C (m x n, m >= n, dense or CSR), where I is the
+ * m x n matrix [I_n; 0] (Deng & Xu, "Recycling singular and projection
+ * subspaces for pseudospectra computation", Sec. 1, eqs. (defSquare) and
+ * (defSquareSVD)).  It reports sigma_min and the membership of each point in
+ * the epsilon-pseudospectrum, sigma_min < epsilon (strict), for a list of
+ * epsilon levels.
+ *
+ * The method is the paper's Alg. 5 (psPrecRecy): Ritz singular pairs from a
+ * recycled singular subspace (Sec. 2.2, Alg. 1), a residual acceptance test
+ * (eq. (tolC)), and for rejected points a block LOBPCG-SVD (supplement,
+ * Alg. SM1.1) preconditioned by the two-level preconditioner of eq.
+ * (twolevel), whose projection subspace is recycled the same way (Sec. 3.2,
+ * Alg. 4), with the adaptive subspace update of Alg. 2 and the
+ * base-preconditioner rebuild rule of eq. (tauRecycle).  Every numerical
+ * step runs in HIP kernels on the GPU in complex128.
+ *
+ * Conventions
+ *  - Complex numbers are interleaved (re, im) doubles.  Dense matrices are
+ *    column-major with a leading dimension.
+ *  - Grid: x_i = re_lo + i (re_hi - re_lo)/(nx - 1), y_j likewise, both
+ *    ends included (x_0 = re_lo when nx = 1); point (i, j) has index
+ *    j * nx + i in every per-point array.
+ *  - Ownership: input arrays are borrowed for the duration of the call (and
+ *    copied to the device unless on_device = 1, in which case they must stay
+ *    valid and unchanged until ps_destroy).  Handles belong to the library
+ *    until the matching *_destroy.  Output arrays are caller-allocated host
+ *    memory.
+ *  - Errors: negative return values are errors and leave outputs undefined;
+ *    PS_WARN_UNCERTIFIED (positive) means every output was written but some
+ *    points hit the LOBPCG iteration cap (see flags).
+ *  - Threading: a ps_matrix must not be used from two threads at once.
+ *    Calls on different handles may run concurrently on different streams.
+ */
+#ifndef PS_H
+#define PS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_matrix ps_matrix; /* device copy of C + recycled stores + preconditioner */
+typedef struct ps_gridh ps_gridh;   /* grid points and traversal plan */
+
+typedef enum {
+    PS_OK = 0,
+    PS_WARN_UNCERTIFIED = 1,
+    PS_EINVAL = -1,
+    PS_ENOMEM = -2,
+    PS_EDEVICE = -3,
+    PS_EBREAKDOWN = -4,
+    PS_EUNSUPPORTED = -5
+} ps_status;
+
+typedef enum { PS_DENSE = 0, PS_CSR = 1 } ps_kind;
+
+/* Input matrix C (m x n, m >= n >= 1). */
+typedef struct {
+    int32_t kind;           /* PS_DENSE or PS_CSR */
+    int64_t m, n;
+    const double* dense;    /* PS_DENSE: 2 * ld * n doubles, column-major */
+    int64_t ld;             /* PS_DENSE: leading dimension >= m */
+    const int64_t* rowptr;  /* PS_CSR: m + 1 entries, rowptr[0] = 0 */
+    const int32_t* colind;  /* PS_CSR: nnz column indices, sorted within each row */
+    const double* vals;     /* PS_CSR: 2 * nnz doubles */
+    int64_t nnz;
+    int32_t on_device;      /* 1: the pointers above are device memory */
+} ps_matrix_desc;
+
+/* Tunables; ps_default_params fills in the defaults.  Symbols follow the
+ * paper (Sec. 4 lists its own values). */
+typedef struct {
+    int32_t r;          /* singular LOBPCG block size r (default 8) */
+    int32_t k_max;      /* cap on the recycled singular dimension p r (default 32) */
+    int32_t rbar;       /* projection block size rbar (default 16) */
+    int32_t kbar_max;   /* cap on the recycled projection dimension (default 64) */
+    int32_t max_iters;  /* LOBPCG iteration cap (default 300) */
+    int32_t precond;    /* 0: K = I; 1: two-level K_E with recycled projection
+                           subspace on a base preconditioner (default 1) */
+    int32_t tiles_x;    /* grid-front partition: tiles along x (0 = auto) */
+    int32_t tiles_y;    /* tiles along y (0 = auto) */
+    int32_t batch;      /* b of the batch-zigzag traversal (default 20) */
+    int32_t recycle;    /* 1: recycled path; 0: plain per-point LOBPCG from a
+                           seeded random start (the comparison solver) */
+    double eta;         /* acceptance tolerance of eq. (tolC) (default 1e-6) */
+    double eta_svd;     /* LOBPCG convergence tolerance, eq. (tolSVD) (1e-9) */
+    double eta_proj;    /* projection test tolerance, eq. (tolTz) (1e-4) */
+    double omega;       /* pruning threshold of eq. (omegaCond) (1.6) */
+    double tau_min;     /* eq. (tauRecycle) lower threshold (1e-3) */
+    double tau_max;     /* eq. (tauRecycle) upper threshold (30) */
+    double zdag_re;     /* first base-preconditioner site; NaN = region centre */
+    double zdag_im;
+    uint64_t seed;      /* seed of random start blocks */
+} ps_params;
+
+typedef struct {
+    int64_t points;        /* grid points evaluated */
+    int64_t accepted;      /* accepted by the recycled Ritz test (tolC) */
+    int64_t refined;       /* refined by LOBPCG-SVD (recycling points) */
+    int64_t uncertified;   /* LOBPCG hit max_iters */
+    int64_t lobpcg_iters;  /* singular LOBPCG iterations, summed over points */
+    int64_t proj_accepted; /* projection Ritz vectors accepted (tolTz) */
+    int64_t proj_refined;  /* projection LOBPCG runs */
+    int64_t proj_iters;
+    int64_t rebuilds;      /* base-preconditioner constructions */
+    int64_t mv_M;          /* operator column-applies of C or C^* */
+    int64_t sv_F;          /* column solves / applies with F^{-1}, F^{-*} */
+    int64_t rounds;        /* scheduler rounds */
+    double t_total_ms;     /* wall time of ps_eval */
+    double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
+} ps_stats;
+
+/* Per-point flag bits written to `flags`. */
+#define PS_FLAG_ACCEPTED 1u     /* sigma from the recycled Ritz value */
+#define PS_FLAG_REFINED 2u      /* sigma from LOBPCG-SVD */
+#define PS_FLAG_UNCERTIFIED 4u  /* LOBPCG hit the iteration cap */
+#define PS_FLAG_PROJ_REFINED 8u /* projection subspace refined here */
+#define PS_FLAG_REBUILD 16u     /* base preconditioner rebuilt here */
+
+void ps_default_params(ps_params* p);
+
+/* Upload C, prepare the operators and the (empty) recycled stores.
+ * hip_stream: the hipStream_t all work is issued on (NULL = default).
+ * Errors: PS_EINVAL (m < n, n < 1, bad CSR, NULL pointers, bad params),
+ * PS_ENOMEM, PS_EDEVICE. */
+ps_status ps_create(const ps_matrix_desc* desc, const ps_params* params, void* hip_stream,
+                    ps_matrix** out);
+
+/* A grid over [re_lo, re_hi] x [im_lo, im_hi] with nx x ny points (ends
+ * included).  Errors: PS_EINVAL (nx < 1, ny < 1, non-finite bounds). */
+ps_status ps_grid(double re_lo, double re_hi, double im_lo, double im_hi, int32_t nx,
+                  int32_t ny, ps_gridh** out);
+
+/* Evaluate sigma_min(C - z I) on every grid point.
+ * sigma:  nx*ny doubles (host), sigma[j*nx+i].
+ * member: n_eps*nx*ny bytes (host) or NULL; member[e*nx*ny + p] = sigma[p] < eps[e].
+ * flags:  nx*ny bytes (host) or NULL; PS_FLAG_* bits.
+ * stats:  or NULL.
+ * Each call starts from empty recycled stores, so results do not depend on
+ * earlier calls.  Errors: PS_EINVAL, PS_ENOMEM, PS_EDEVICE, PS_EBREAKDOWN. */
+ps_status ps_eval(ps_matrix* h, const ps_gridh* g, const double* eps, int32_t n_eps,
+                  double* sigma, uint8_t* member, uint8_t* flags, ps_stats* stats);
+
+void ps_grid_destroy(ps_gridh* g);
+void ps_destroy(ps_matrix* h);
+const char* ps_strerror(ps_status s);
+
+/* Text of the last error raised on this thread (empty if none). */
+const char* ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PS_H */

@@ -1,0 +1,253 @@
+"""Python binding of the MI355X pseudospectra library (libps.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libps.so``.  The names follow the C ABI in ``include/ps.h``:
+``ps_create``, ``ps_grid``, ``ps_eval``, ``ps_destroy``.  Importing this
+package never builds anything; ``build.build()`` (or
+``__graft_entry__.build()``) compiles the library.  If ``libps.so`` is missing
+the functions raise: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libps.so")
+
+PS_OK = 0
+PS_WARN_UNCERTIFIED = 1
+PS_DENSE = 0
+PS_CSR = 1
+FLAG_ACCEPTED = 1
+FLAG_REFINED = 2
+FLAG_UNCERTIFIED = 4
+FLAG_PROJ_REFINED = 8
+FLAG_REBUILD = 16
+
+
+class ps_matrix_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("dense", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64), ("on_device", ctypes.c_int32)]
+
+
+class ps_params(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("k_max", ctypes.c_int32), ("rbar", ctypes.c_int32),
+                ("kbar_max", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("recycle", ctypes.c_int32), ("eta", ctypes.c_double), ("eta_svd", ctypes.c_double),
+                ("eta_proj", ctypes.c_double), ("omega", ctypes.c_double), ("tau_min", ctypes.c_double),
+                ("tau_max", ctypes.c_double), ("zdag_re", ctypes.c_double), ("zdag_im", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class ps_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "points", "accepted", "refined", "uncertified", "lobpcg_iters", "proj_accepted",
+        "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds")] + \
+        [(n, ctypes.c_double) for n in ("t_total_ms", "t_ritz_ms", "t_lobpcg_ms", "t_update_ms",
+                                        "t_precond_ms")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libps.so not built: run paper_2606_26785_amd/build.py (no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.ps_default_params.argtypes = [ctypes.POINTER(ps_params)]
+    lib.ps_default_params.restype = None
+    lib.ps_create.argtypes = [ctypes.POINTER(ps_matrix_desc), ctypes.POINTER(ps_params), P,
+                              ctypes.POINTER(P)]
+    lib.ps_create.restype = ctypes.c_int
+    lib.ps_grid.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P)]
+    lib.ps_grid.restype = ctypes.c_int
+    lib.ps_eval.argtypes = [P, P, P, ctypes.c_int32, P, P, P, ctypes.POINTER(ps_stats)]
+    lib.ps_eval.restype = ctypes.c_int
+    lib.ps_grid_destroy.argtypes = [P]
+    lib.ps_grid_destroy.restype = None
+    lib.ps_destroy.argtypes = [P]
+    lib.ps_destroy.restype = None
+    lib.ps_strerror.argtypes = [ctypes.c_int]
+    lib.ps_strerror.restype = ctypes.c_char_p
+    lib.ps_last_error.argtypes = []
+    lib.ps_last_error.restype = ctypes.c_char_p
+    lib.ps_debug_apply.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int32, P]
+    lib.ps_debug_apply.restype = ctypes.c_int
+    lib.ps_debug_norm.argtypes = [P]
+    lib.ps_debug_norm.restype = ctypes.c_double
+    _lib = lib
+    return lib
+
+
+class PSError(RuntimeError):
+    def __init__(self, status, where):
+        lib = load()
+        msg = "%s: %s (%s)" % (where, lib.ps_strerror(status).decode(), lib.ps_last_error().decode())
+        super().__init__(msg)
+        self.status = status
+
+
+def _check(status, where):
+    if status < 0:
+        raise PSError(status, where)
+    return status
+
+
+def default_params(**overrides) -> ps_params:
+    p = ps_params()
+    load().ps_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Matrix:
+    """A ps_matrix handle (owns the device copy of C and the solver state)."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def close(self):
+        if self.handle:
+            load().ps_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def norm_estimate(self) -> float:
+        return float(load().ps_debug_norm(self.handle))
+
+
+class Grid:
+    def __init__(self, handle, nx, ny):
+        self.handle = handle
+        self.nx = nx
+        self.ny = ny
+
+    def close(self):
+        if self.handle:
+            load().ps_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(a.data_ptr())
+
+
+def ps_create(dense=None, csr=None, m=None, n=None, params: ps_params | None = None, stream=None) -> Matrix:
+    """Create a handle from a dense complex matrix (host numpy array, any
+    order) or a CSR triple (rowptr int64, colind int32, vals complex128)."""
+    lib = load()
+    d = ps_matrix_desc()
+    keep = []
+    if dense is not None:
+        A = np.asfortranarray(np.asarray(dense), dtype=np.complex128)
+        keep.append(A)
+        d.kind = PS_DENSE
+        d.m, d.n = A.shape
+        d.ld = A.shape[0]
+        d.dense = _ptr(A)
+        d.on_device = 0
+    else:
+        rowptr, colind, vals = csr
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        colind = np.ascontiguousarray(colind, dtype=np.int32)
+        vals = np.ascontiguousarray(vals, dtype=np.complex128)
+        keep += [rowptr, colind, vals]
+        d.kind = PS_CSR
+        d.m = int(m)
+        d.n = int(n)
+        d.rowptr = _ptr(rowptr)
+        d.colind = _ptr(colind)
+        d.vals = _ptr(vals)
+        d.nnz = int(vals.size)
+        d.on_device = 0
+    h = ctypes.c_void_p()
+    s = ctypes.c_void_p(stream) if stream is not None else ctypes.c_void_p(0)
+    _check(lib.ps_create(ctypes.byref(d), ctypes.byref(params) if params is not None else None, s,
+                         ctypes.byref(h)), "ps_create")
+    mat = Matrix(h, keep)
+    mat.shape = (int(d.m), int(d.n))
+    return mat
+
+
+def ps_grid(re_lo, re_hi, im_lo, im_hi, nx, ny) -> Grid:
+    h = ctypes.c_void_p()
+    _check(load().ps_grid(float(re_lo), float(re_hi), float(im_lo), float(im_hi), int(nx), int(ny),
+                          ctypes.byref(h)), "ps_grid")
+    return Grid(h, int(nx), int(ny))
+
+
+@dataclass
+class EvalResult:
+    sigma: np.ndarray        # (ny, nx) flattened as j * nx + i
+    member: np.ndarray       # (n_eps, npts) uint8
+    flags: np.ndarray        # npts uint8
+    stats: dict
+    status: int
+
+
+def ps_eval(mat: Matrix, grid: Grid, eps=()) -> EvalResult:
+    lib = load()
+    npts = grid.nx * grid.ny
+    eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(-1))
+    sigma = np.empty(npts, dtype=np.float64)
+    member = np.empty((max(eps.size, 1), npts), dtype=np.uint8)
+    flags = np.empty(npts, dtype=np.uint8)
+    st = ps_stats()
+    status = lib.ps_eval(mat.handle, grid.handle, _ptr(eps) if eps.size else None, int(eps.size),
+                         _ptr(sigma), _ptr(member), _ptr(flags), ctypes.byref(st))
+    _check(status, "ps_eval")
+    return EvalResult(sigma, member[:eps.size], flags, st.as_dict(), status)
+
+
+def ps_destroy(mat: Matrix):
+    mat.close()
+
+
+def debug_apply(mat: Matrix, X: np.ndarray, z: complex = 0j, herm: bool = False) -> np.ndarray:
+    """Y = C(z) X (herm False) or C(z)^* X (herm True) on the device (test hook)."""
+    X = np.asfortranarray(X, dtype=np.complex128)
+    w = X.shape[1]
+    m, n = mat.shape
+    Y = np.empty((n if herm else m, w), dtype=np.complex128, order="F")
+    _check(load().ps_debug_apply(mat.handle, int(herm), float(np.real(z)), float(np.imag(z)), _ptr(X), w,
+                                 _ptr(Y)), "ps_debug_apply")
+    return Y
+
+
+def create_from_workload(wl, params: ps_params | None = None, stream=None) -> Matrix:
+    """Handle for a ``workloads.Workload``."""
+    if wl.kind == "dense":
+        return ps_create(dense=wl.dense, params=params, stream=stream)
+    return ps_create(csr=(wl.rowptr, wl.colind, wl.vals), m=wl.m, n=wl.n, params=params, stream=stream)

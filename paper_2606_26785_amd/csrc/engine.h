@@ -1,0 +1,179 @@
+// Host-side engine: device buffers, operators, the grid-front scheduler and
+// the batched solver steps.  Internal to the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdexcept>
+#include <string>
+#include <vector>
+#include "kernels.h"
+#include "../../include/ps.h"
+
+struct DeviceError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+struct InvalidArg : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(x)                                                                            \
+    do {                                                                                     \
+        hipError_t e_ = (x);                                                                 \
+        if (e_ != hipSuccess)                                                                \
+            throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_) + " at " +      \
+                              __FILE__ + ":" + std::to_string(__LINE__));                    \
+    } while (0)
+
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t cnt) {
+        if (cnt <= n && p) return;
+        release();
+        if (cnt == 0) cnt = 1;
+        HIPCHK(hipMalloc((void**)&p, cnt * sizeof(T)));
+        n = cnt;
+    }
+    void zero(hipStream_t s) { if (p) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), s)); }
+    operator T*() const { return p; }
+};
+
+template <class T>
+struct HBuf {  // pinned host buffer
+    T* p = nullptr;
+    size_t n = 0;
+    HBuf() = default;
+    HBuf(const HBuf&) = delete;
+    HBuf& operator=(const HBuf&) = delete;
+    ~HBuf() { if (p) (void)hipHostFree(p); }
+    void alloc(size_t cnt) {
+        if (cnt <= n && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        if (cnt == 0) cnt = 1;
+        HIPCHK(hipHostMalloc((void**)&p, cnt * sizeof(T), hipHostMallocDefault));
+        n = cnt;
+    }
+    T& operator[](size_t i) { return p[i]; }
+};
+
+// The matrix C on the device, with applies of C(z) = C - z S and C(z)^*.
+struct Operator {
+    int kind = PS_DENSE;
+    int64_t m = 0, n = 0, nnz = 0;
+    DBuf<zd> A, AH;                     // dense C (m x n, ld m) and C^* (n x m, ld n)
+    DBuf<int64_t> rp, rpH;              // CSR of C and of C^*
+    DBuf<int32_t> ci, ciH;
+    DBuf<zd> v, vH;
+    double normC = 0.0;                 // ||C||_2 estimate (power iteration, x1.01)
+};
+
+struct ps_gridh {
+    double re_lo, re_hi, im_lo, im_hi;
+    int32_t nx, ny;
+};
+
+struct Tile {
+    std::vector<int> order;   // grid point indices in traversal order
+    size_t cursor = 0;
+    int k = 0;                // recycled singular dimension
+    bool done() const { return cursor >= order.size(); }
+};
+
+struct Engine {
+    hipStream_t st = nullptr;
+    ps_params P{};
+    Operator op;
+
+    // ---- per-eval sizing
+    int T = 0;         // tile slots
+    int r = 8, K = 32; // block size, recycled cap
+    int B = 20;        // ritz window per round
+    int64_t n = 0, m = 0;
+
+    // singular store (primary + update scratch)
+    DBuf<zd> sV, sW1, sW3, sW4, uV, uW1, uW3, uW4;
+    DBuf<zd> sRA, sRres;
+    DBuf<zdd> gdd;        // Gram workspace (per tile, (4K)^2)
+    DBuf<int> d_k, d_q, d_l;
+
+    // LOBPCG state (per tile)
+    DBuf<zd> S, CS, Sn, CSn, Wres, Xw, Tn1, Tn2, Tn3;
+    DBuf<zd> Rsm, GX, GP, Csm, Tsm, Qt, Upp, Ucoef, X0c;
+    DBuf<double> xi, nrm2, xi_out;
+    DBuf<uint32_t> mask;
+    DBuf<int> cdim, d_list, d_list2, d_jobsrc;
+    DBuf<zd> d_z;         // per tile current z
+
+    // ritz jobs
+    DBuf<int> j_tile;
+    DBuf<zd> j_z, j_G;
+    DBuf<double> j_nrm, j_xi, j_res;
+    DBuf<uint8_t> j_acc;
+
+    // workspaces
+    DBuf<char> gram_ws;
+    size_t gram_ws_bytes = 0;
+    DBuf<zd> apply_ws;
+    int apply_splitk = 1;
+    DBuf<double> norm_ws;
+
+    // pinned host mirrors
+    HBuf<uint8_t> h_acc;
+    HBuf<double> h_xi, h_nrm2, h_small;
+    HBuf<zd> h_C;
+    HBuf<int> h_list;
+    HBuf<zd> h_z;
+
+    ps_stats stats{};
+    std::vector<Tile> tiles;
+    std::vector<zd> zs;       // grid points of the current eval
+
+    // ---- setup
+    void create(const ps_matrix_desc* d, const ps_params* p, hipStream_t s);
+    void estimate_norm();
+    void size_for(int tiles);
+
+    // ---- operator applies on tiles (columns w per tile)
+    // Y (m rows) = C(z) X (n rows);  herm: Y (n rows) = C(z)^* X (m rows)
+    void apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xstride, int64_t ldx, zd* Y,
+               int64_t ystride, int64_t ldy, int w, const zd* dz);
+
+    // ---- building blocks
+    void upload_list(const std::vector<int>& L, DBuf<int>& dst);
+    void gram(const int* dlist, int nt, const BlockList& A, const BlockList& Bl, int camax, int cbmax, void* out,
+              int64_t strideOut, int ldOut, bool dd, bool upper);
+    void gemm_ts(const int* dlist, int nt, const BlockList& A, int camax, const zd* G, int64_t strideG, int ldG,
+                 const int* cbdims, int cbmul, int cb, zd* Y, int64_t strideY, int64_t ldY, int64_t rows,
+                 double alpha, double beta);
+    void colnorm2(const int* dlist, int nt, const BlockList& A, int camax, double* out, int ldo);
+    void orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, int64_t wstride, int64_t ldw,
+                        int64_t rows, int cols, const BlockList* against, int against_max, uint64_t seed);
+    void r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul, int cfixed,
+                  zd* R, int64_t strideR, int ldR);
+
+    // ---- algorithm steps
+    void lobpcg(const std::vector<int>& L, std::vector<double>& sigma, std::vector<int>& iters,
+                std::vector<int>& ok, uint64_t seed);
+    void update_store(const std::vector<int>& L);
+    void upload_k();
+    void refresh_store(const std::vector<int>& L);
+    ps_status eval(const ps_gridh* g, const double* eps, int n_eps, double* sigma, uint8_t* member,
+                   uint8_t* flags, ps_stats* st_out);
+};
+
+BlockList bl_empty(int64_t rows);
+void bl_add(BlockList& L, const zd* ptr, int64_t stride, int64_t ld, int ncols, const int* dims, int mul,
+            int64_t brows = 0, const int* coff = nullptr, int coffmul = 0);
+void launch_gather(const int* list, int nt, const int* srcidx, const zd* src, int64_t sstride, zd* dst,
+                   int64_t dstride, int64_t count, hipStream_t s);

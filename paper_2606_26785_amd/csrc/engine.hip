@@ -1,0 +1,613 @@
+// Host-side engine: operator setup, batched building blocks, LOBPCG-SVD,
+// the recycled-subspace update and the grid-front scheduler (Alg. 5 per tile).
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+static const double EPSM = 2.220446049250313e-16;
+
+// ---------------------------------------------------------------------------
+BlockList bl_empty(int64_t rows)
+{
+    BlockList L;
+    memset(&L, 0, sizeof(L));
+    L.rows = rows;
+    return L;
+}
+void bl_add(BlockList& L, const zd* ptr, int64_t stride, int64_t ld, int ncols, const int* dims, int mul,
+            int64_t brows, const int* coff, int coffmul)
+{
+    int b = L.nb++;
+    L.ptr[b] = ptr;
+    L.stride[b] = stride;
+    L.ld[b] = ld;
+    L.ncols[b] = ncols;
+    L.dims[b] = dims;
+    L.mul[b] = mul;
+    L.brows[b] = brows;
+    L.coff[b] = coff;
+    L.coffmul[b] = coffmul;
+}
+
+__global__ void k_gather(const int* list, const int* srcidx, const zd* src, int64_t sstride, zd* dst,
+                         int64_t dstride, int64_t count)
+{
+    const int t = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    dst[(size_t)t * dstride + e] = src[(size_t)srcidx[t] * sstride + e];
+}
+void launch_gather(const int* list, int nt, const int* srcidx, const zd* src, int64_t sstride, zd* dst,
+                   int64_t dstride, int64_t count, hipStream_t s)
+{
+    if (nt <= 0 || count <= 0) return;
+    dim3 g((unsigned)((count + 255) / 256), nt);
+    hipLaunchKernelGGL(k_gather, g, dim3(256), 0, s, list, srcidx, src, sstride, dst, dstride, count);
+}
+
+// conjugate transpose: B (n x m, ld n) = A^* (A m x n, ld lda)
+__global__ void k_conj_transpose(const zd* A, int64_t lda, int64_t m, int64_t n, zd* B)
+{
+    __shared__ zd t[32][33];
+    int64_t bi = (int64_t)blockIdx.x * 32, bj = (int64_t)blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        int64_t i = bi + threadIdx.x, j = bj + k;
+        if (i < m && j < n) t[k][threadIdx.x] = A[i + j * lda];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        int64_t j = bj + threadIdx.x, i = bi + k;
+        if (i < m && j < n) B[j + i * n] = zconj(t[threadIdx.x][k]);
+    }
+}
+
+// sqrt-and-invert helper for column scaling: d holds squared norms
+__global__ void k_scale_cols_rsqrt(const int* list, zd* A, int64_t stride, int64_t lda, int64_t rows, int cols,
+                                   const double* d, int ldd)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    int64_t i = e % rows, j = e / rows;
+    double v = d[(size_t)tile * ldd + j];
+    double f = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    zd* p = A + (size_t)tile * stride + i + j * lda;
+    *p = zscale(*p, f);
+}
+
+// ---------------------------------------------------------------------------
+void Engine::upload_list(const std::vector<int>& L, DBuf<int>& dst)
+{
+    h_list.alloc(L.size() + 1);
+    for (size_t i = 0; i < L.size(); ++i) h_list[i] = L[i];
+    dst.alloc(std::max<size_t>(L.size(), 1));
+    if (!L.empty()) HIPCHK(hipMemcpyAsync(dst.p, h_list.p, L.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    // h_list is reused by the next call: wait for the copy
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+void Engine::gram(const int* dlist, int nt, const BlockList& A, const BlockList& Bl, int camax, int cbmax,
+                  void* out, int64_t strideOut, int ldOut, bool dd, bool upper)
+{
+    if (nt <= 0) return;
+    GramArgs g;
+    memset(&g, 0, sizeof(g));
+    g.list = dlist;
+    g.ntiles = nt;
+    g.A = A;
+    g.B = Bl;
+    g.camax = camax;
+    g.cbmax = cbmax;
+    g.out = out;
+    g.strideOut = strideOut;
+    g.ldOut = ldOut;
+    g.part = gram_ws.p;
+    g.dd = dd ? 1 : 0;
+    g.hermitian_upper_only = upper ? 1 : 0;
+    size_t esz = dd ? sizeof(zdd) : sizeof(zd);
+    // rows per chunk: enough chunks to fill the GPU, within the workspace
+    int64_t rows = A.rows;
+    int nout = ((camax + 31) / 32) * ((cbmax + 31) / 32);
+    int64_t want = std::max<int64_t>(1, 2048 / std::max(1, nt * nout));
+    int64_t cap = (int64_t)(gram_ws_bytes / ((size_t)nt * camax * cbmax * esz));
+    if (cap < 1) throw DeviceError("gram workspace too small");
+    int64_t nch = std::min<int64_t>(std::max<int64_t>(want, 1), cap);
+    int64_t cr = (rows + nch - 1) / nch;
+    cr = std::max<int64_t>(32, (cr + 31) / 32 * 32);
+    while ((rows + cr - 1) / cr > cap) cr += 32;
+    g.chunk_rows = (int)cr;
+    launch_gram(g, st);
+}
+
+void Engine::gemm_ts(const int* dlist, int nt, const BlockList& A, int camax, const zd* G, int64_t strideG, int ldG,
+                     const int* cbdims, int cbmul, int cb, zd* Y, int64_t strideY, int64_t ldY, int64_t rows,
+                     double alpha, double beta)
+{
+    if (nt <= 0) return;
+    GemmTSArgs g;
+    memset(&g, 0, sizeof(g));
+    g.list = dlist;
+    g.ntiles = nt;
+    g.A = A;
+    g.G = G;
+    g.strideG = strideG;
+    g.ldG = ldG;
+    g.cbdims = cbdims;
+    g.cbmul = cbmul;
+    g.cb = cb;
+    g.Y = Y;
+    g.strideY = strideY;
+    g.ldY = ldY;
+    g.rows = rows;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.camax = camax;
+    g.cbmax = cbdims ? K * cbmul : cb;
+    if (cbdims) g.cbmax = std::max(g.cbmax, cb);
+    launch_gemm_ts(g, st);
+}
+
+void Engine::colnorm2(const int* dlist, int nt, const BlockList& A, int camax, double* out, int ldo)
+{
+    if (nt <= 0) return;
+    NormArgs a;
+    memset(&a, 0, sizeof(a));
+    a.list = dlist;
+    a.ntiles = nt;
+    a.A = A;
+    a.camax = camax;
+    a.out = out;
+    a.ldo = ldo;
+    a.part = norm_ws.p;
+    int64_t nch = std::max<int64_t>(1, std::min<int64_t>(256 / std::max(1, nt) + 1,
+                                                         (int64_t)(norm_ws.n / ((size_t)nt * camax))));
+    int64_t cr = (A.rows + nch - 1) / nch;
+    cr = std::max<int64_t>(64, cr);
+    while ((A.rows + cr - 1) / cr * (int64_t)nt * camax > (int64_t)norm_ws.n) cr *= 2;
+    a.chunk_rows = (int)cr;
+    launch_colnorm2(a, st);
+}
+
+// R (c x c upper) of the tall matrix A from a double-double Gram matrix and
+// a double-double Cholesky (mixed-precision Cholesky QR): R^* R = A^* A to
+// double-double accuracy, so R equals the R factor of a backward-stable QR
+// of A up to rounding of R itself.
+void Engine::r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul,
+                      int cfixed, zd* R, int64_t strideR, int ldR)
+{
+    if (nt <= 0) return;
+    gram(dlist, nt, A, A, cmax, cmax, gdd.p, (int64_t)cmax * cmax, cmax, true, true);
+    CholArgs c;
+    memset(&c, 0, sizeof(c));
+    c.list = dlist;
+    c.cdim = cdims;
+    c.cmul = cmul;
+    c.c = cfixed;
+    c.G = gdd.p;
+    c.strideG = (int64_t)cmax * cmax;
+    c.ldG = cmax;
+    c.R = R;
+    c.strideR = strideR;
+    c.ldR = ldR;
+    launch_chol_dd(c, nt, st);
+}
+
+// Orthonormalise the cols-column block W of each tile in L (in place), and
+// make it orthogonal to `against` if given: repeated block projection
+// followed by SVQB on the column-scaled block; directions that vanish are
+// refilled with seeded random vectors and orthonormalised again.
+void Engine::orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, int64_t wstride, int64_t ldw,
+                            int64_t rows, int cols, const BlockList* against, int against_max, uint64_t seed)
+{
+    const int nt = (int)L.size();
+    if (nt == 0) return;
+    BlockList Wl = bl_empty(rows);
+    bl_add(Wl, W, wstride, ldw, cols, nullptr, 0);
+    for (int pass = 0; pass < 6; ++pass) {
+        if (against) {
+            for (int rep = 0; rep < 2; ++rep) {
+                gram(dlist, nt, *against, Wl, against_max, cols, Csm.p, (int64_t)K * 3 * r, against_max, false,
+                     false);
+                gemm_ts(dlist, nt, *against, against_max, Csm.p, (int64_t)K * 3 * r, against_max, nullptr, 0, cols,
+                        W, wstride, ldw, rows, -1.0, 1.0);
+            }
+        }
+        colnorm2(dlist, nt, Wl, cols, nrm2.p, 3 * r);
+        {
+            dim3 g((unsigned)((rows * cols + 255) / 256), nt);
+            hipLaunchKernelGGL(k_scale_cols_rsqrt, g, dim3(256), 0, st, dlist, W, wstride, ldw, rows, cols, nrm2.p,
+                               3 * r);
+        }
+        r_factor(dlist, nt, Wl, cols, nullptr, 0, cols, Rsm.p, (int64_t)9 * r * r, 3 * r);
+        SvqbArgs sa;
+        memset(&sa, 0, sizeof(sa));
+        sa.list = dlist;
+        sa.r = cols;
+        sa.max_sweeps = 40;
+        sa.drop = 1e-10;
+        sa.R = Rsm.p;
+        sa.strideR = (int64_t)9 * r * r;
+        sa.ldR = 3 * r;
+        sa.T = Tsm.p;
+        sa.strideT = (int64_t)9 * r * r;
+        sa.ldT = 3 * r;
+        sa.mask = mask.p;
+        launch_svqb(sa, nt, st);
+        gemm_ts(dlist, nt, Wl, cols, Tsm.p, (int64_t)9 * r * r, 3 * r, nullptr, 0, cols, Tn1.p, (int64_t)m * 3 * r,
+                m, rows, 1.0, 0.0);
+        launch_copy_cols(dlist, nt, Tn1.p, (int64_t)m * 3 * r, m, W, wstride, ldw, rows, cols, st);
+        launch_randfill(dlist, nt, W, wstride, ldw, rows, cols, mask.p, seed + 7919ull * pass, st);
+        // check whether any direction was refilled
+        h_small.alloc(T + 1);
+        HIPCHK(hipMemcpyAsync(h_small.p, mask.p, sizeof(uint32_t) * T, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const uint32_t* hm = (const uint32_t*)h_small.p;
+        bool any = false;
+        for (int t : L) any |= (hm[t] != 0);
+        if (!any && pass >= 1) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+void Engine::apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xstride, int64_t ldx, zd* Y,
+                   int64_t ystride, int64_t ldy, int w, const zd* dz)
+{
+    if (nt <= 0) return;
+    stats.mv_M += (int64_t)nt * w;
+    if (op.kind == PS_DENSE) {
+        DenseApplyArgs a;
+        memset(&a, 0, sizeof(a));
+        if (!herm) { a.A = op.A.p; a.lda = op.m; a.m = op.m; a.K = op.n; }
+        else { a.A = op.AH.p; a.lda = op.n; a.m = op.n; a.K = op.m; }
+        a.list = dlist;
+        a.ntiles = nt;
+        a.X = X;
+        a.xstride = xstride;
+        a.ldx = ldx;
+        a.Y = Y;
+        a.ystride = ystride;
+        a.ldy = ldy;
+        a.w = w;
+        a.z = dz;
+        a.conjz = herm ? 1 : 0;
+        a.nshift = op.n;
+        a.part = apply_ws.p;
+        int64_t N = (int64_t)nt * w;
+        a.splitk = (int)std::max<int64_t>(1, (int64_t)(apply_ws.n / ((size_t)a.m * N)));
+        launch_dense_apply(a, st);
+    } else {
+        CsrApplyArgs a;
+        memset(&a, 0, sizeof(a));
+        if (!herm) { a.rowptr = op.rp.p; a.colind = op.ci.p; a.vals = op.v.p; a.m = op.m; }
+        else { a.rowptr = op.rpH.p; a.colind = op.ciH.p; a.vals = op.vH.p; a.m = op.n; }
+        a.list = dlist;
+        a.ntiles = nt;
+        a.X = X;
+        a.xstride = xstride;
+        a.ldx = ldx;
+        a.Y = Y;
+        a.ystride = ystride;
+        a.ldy = ldy;
+        a.w = w;
+        a.z = dz;
+        a.conjz = herm ? 1 : 0;
+        a.nshift = op.n;
+        launch_csr_apply(a, st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+void Engine::create(const ps_matrix_desc* d, const ps_params* p, hipStream_t s)
+{
+    st = s;
+    P = *p;
+    op.kind = d->kind;
+    op.m = d->m;
+    op.n = d->n;
+    small_kernels_init();
+    {
+        // LDS of the per-workgroup kernels: Ritz (2 k^2 complex) and the
+        // rotations ((k^2 + 7 r^2 + 2 r k) complex), plus static arrays
+        size_t need = std::max<size_t>((size_t)2 * P.k_max * P.k_max,
+                                       (size_t)P.k_max * P.k_max + 7 * P.r * P.r + 2 * P.r * P.k_max) * sizeof(zd);
+        if (need + 4096 > (size_t)small_kernels_max_lds())
+            throw InvalidArg("k_max too large for this device's LDS per workgroup");
+    }
+    if (d->kind == PS_DENSE) {
+        size_t cnt = (size_t)d->m * d->n;
+        op.A.alloc(cnt);
+        op.AH.alloc(cnt);
+        hipMemcpyKind kind = d->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIPCHK(hipMemcpy2DAsync(op.A.p, sizeof(zd) * d->m, d->dense, sizeof(zd) * d->ld, sizeof(zd) * d->m, d->n,
+                                kind, st));
+        dim3 g((unsigned)((d->m + 31) / 32), (unsigned)((d->n + 31) / 32));
+        hipLaunchKernelGGL(k_conj_transpose, g, dim3(32, 8), 0, st, op.A.p, (int64_t)d->m, d->m, d->n, op.AH.p);
+        HIPCHK(hipGetLastError());
+    } else {
+        // CSR of C and of C^* (the transpose is built once on the host)
+        int64_t mm = d->m, nn = d->n, nnz = d->nnz;
+        std::vector<int64_t> rp(mm + 1);
+        std::vector<int32_t> ci(nnz);
+        std::vector<zd> v(nnz);
+        hipMemcpyKind kind = d->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+        HIPCHK(hipMemcpy(rp.data(), d->rowptr, sizeof(int64_t) * (mm + 1), kind));
+        HIPCHK(hipMemcpy(ci.data(), d->colind, sizeof(int32_t) * nnz, kind));
+        HIPCHK(hipMemcpy(v.data(), d->vals, sizeof(zd) * nnz, kind));
+        if (rp[0] != 0 || rp[mm] != nnz) throw InvalidArg("CSR rowptr inconsistent with nnz");
+        for (int64_t i = 0; i < mm; ++i) {
+            if (rp[i + 1] < rp[i]) throw InvalidArg("CSR rowptr not monotone");
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+                if (ci[q] < 0 || ci[q] >= nn) throw InvalidArg("CSR column index out of range");
+                if (q > rp[i] && ci[q] <= ci[q - 1]) throw InvalidArg("CSR columns not sorted/unique");
+                if (!std::isfinite(v[q].x) || !std::isfinite(v[q].y)) throw InvalidArg("non-finite entry");
+            }
+        }
+        std::vector<int64_t> rpH(nn + 1, 0);
+        for (int64_t q = 0; q < nnz; ++q) rpH[ci[q] + 1]++;
+        for (int64_t j = 0; j < nn; ++j) rpH[j + 1] += rpH[j];
+        std::vector<int32_t> ciH(nnz);
+        std::vector<zd> vH(nnz);
+        std::vector<int64_t> pos(rpH.begin(), rpH.end() - 1);
+        for (int64_t i = 0; i < mm; ++i)
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+                int64_t o = pos[ci[q]]++;
+                ciH[o] = (int32_t)i;
+                vH[o] = zconj(v[q]);
+            }
+        op.nnz = nnz;
+        op.rp.alloc(mm + 1); op.ci.alloc(nnz); op.v.alloc(nnz);
+        op.rpH.alloc(nn + 1); op.ciH.alloc(nnz); op.vH.alloc(nnz);
+        HIPCHK(hipMemcpy(op.rp.p, rp.data(), sizeof(int64_t) * (mm + 1), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(op.ci.p, ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(op.v.p, v.data(), sizeof(zd) * nnz, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(op.rpH.p, rpH.data(), sizeof(int64_t) * (nn + 1), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(op.ciH.p, ciH.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(op.vH.p, vH.data(), sizeof(zd) * nnz, hipMemcpyHostToDevice));
+    }
+    n = op.n;
+    m = op.m;
+    r = P.r;
+    K = P.k_max;
+    size_for(1);
+    estimate_norm();
+}
+
+// ||C||_2 by power iteration on C^* C (60 steps, on the device), scaled by 1.01.
+void Engine::estimate_norm()
+{
+    std::vector<int> L0 = {0};
+    upload_list(L0, d_list);
+    launch_randfill(d_list.p, 1, S.p, 0, n, n, 1, nullptr, 0x5eedull, st);
+    double lam = 0.0;
+    for (int it = 0; it < 60; ++it) {
+        apply(false, d_list.p, 1, S.p, 0, n, CS.p, 0, m, 1, nullptr);
+        apply(true, d_list.p, 1, CS.p, 0, m, S.p, 0, n, 1, nullptr);
+        BlockList Ls = bl_empty(n);
+        bl_add(Ls, S.p, 0, n, 1, nullptr, 0);
+        colnorm2(d_list.p, 1, Ls, 1, nrm2.p, 3 * r);
+        h_xi.alloc(8);
+        HIPCHK(hipMemcpyAsync(h_xi.p, nrm2.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        double s2 = h_xi[0];
+        lam = sqrt(s2);  // ||C^* C x|| with ||x|| = 1
+        if (!(s2 > 0)) { lam = 0; break; }
+        dim3 g((unsigned)((n + 255) / 256), 1);
+        hipLaunchKernelGGL(k_scale_cols_rsqrt, g, dim3(256), 0, st, d_list.p, S.p, (int64_t)0, (int64_t)n, (int64_t)n,
+                           1, nrm2.p, 3 * r);
+    }
+    stats.mv_M = 0;
+    op.normC = 1.01 * sqrt(lam);
+}
+
+void Engine::size_for(int tiles)
+{
+    T = tiles;
+    const size_t t = (size_t)tiles;
+    const size_t nk = (size_t)n * K, mk = (size_t)m * K;
+    sV.alloc(t * nk); sW1.alloc(t * mk); sW3.alloc(t * nk); sW4.alloc(t * nk);
+    uV.alloc(t * nk); uW1.alloc(t * mk); uW3.alloc(t * nk); uW4.alloc(t * nk);
+    sRA.alloc(t * 4 * K * K);
+    sRres.alloc(t * 16 * K * K);
+    const int cmax = std::max(4 * K, 3 * r);
+    gdd.alloc(t * cmax * cmax);
+    d_k.alloc(t); d_q.alloc(t); d_l.alloc(t);
+    S.alloc(t * n * 3 * r); Sn.alloc(t * n * 3 * r);
+    CS.alloc(t * m * 3 * r); CSn.alloc(t * m * 3 * r);
+    Wres.alloc(t * n * r); Xw.alloc(t * n * r);
+    Tn1.alloc(t * m * 3 * r); Tn2.alloc(t * n * r); Tn3.alloc(t * n * r);
+    Rsm.alloc(t * 9 * r * r); GX.alloc(t * 9 * r * r); GP.alloc(t * 9 * r * r);
+    Csm.alloc(t * K * 3 * r); Tsm.alloc(t * 9 * r * r);
+    Qt.alloc(t * K * K); Upp.alloc(t * r * r); Ucoef.alloc(t * K * r); X0c.alloc(t * K * r);
+    xi.alloc(t * 3 * r); nrm2.alloc(t * 3 * r); xi_out.alloc(t * 3 * r);
+    mask.alloc(t); cdim.alloc(t); d_list.alloc(t); d_list2.alloc(t); d_jobsrc.alloc(t);
+    d_z.alloc(t);
+    const size_t J = t * B;
+    j_tile.alloc(J); j_z.alloc(J); j_G.alloc(J * K * r);
+    j_nrm.alloc(J); j_xi.alloc(J); j_res.alloc(J); j_acc.alloc(J);
+    gram_ws_bytes = std::max<size_t>((size_t)256 << 20, t * (size_t)cmax * cmax * sizeof(zdd) * 2);
+    gram_ws.alloc(gram_ws_bytes);
+    const size_t maxw = (size_t)std::max(r, P.rbar);
+    apply_ws.alloc((size_t)std::max(m, n) * std::max<size_t>(t * maxw, 64) * 4);
+    norm_ws.alloc(std::max<size_t>(1 << 20, t * 3 * r * 256));
+    h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r)); h_nrm2.alloc(t * 3 * r);
+    h_small.alloc(t * 4 + 8); h_C.alloc(t * K * r + 8); h_list.alloc(t + 1); h_z.alloc(t + J);
+}
+
+// ---------------------------------------------------------------------------
+// LOBPCG-SVD (supplement, Alg. SM1.1) on C(z) for every tile in L, block size
+// r, r_v = 1, preconditioner K = I.  The start block is S[:, 0:r] of each
+// tile; on return S[:, 0:r] holds X and sigma[i] the smallest Ritz value of
+// tile L[i].
+void Engine::lobpcg(const std::vector<int>& Lin, std::vector<double>& sigma, std::vector<int>& iters,
+                    std::vector<int>& okv, uint64_t seed)
+{
+    const int nt0 = (int)Lin.size();
+    sigma.assign(nt0, 0.0);
+    iters.assign(nt0, 0);
+    okv.assign(nt0, 0);
+    if (nt0 == 0) return;
+    std::vector<int> L = Lin;
+    std::vector<int> pos(T, -1);
+    for (int i = 0; i < nt0; ++i) pos[L[i]] = i;
+    upload_list(L, d_list);
+    const int64_t sS = (int64_t)n * 3 * r, sC = (int64_t)m * 3 * r;
+    const int r3 = 3 * r;
+    // X0 orthonormal
+    orthonormalize(L, d_list.p, S.p, sS, n, n, r, nullptr, 0, seed);
+    // CX0, R0, svd -> X1
+    apply(false, d_list.p, (int)L.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
+    BlockList Lcx = bl_empty(m);
+    bl_add(Lcx, CS.p, sC, m, r, nullptr, 0);
+    r_factor(d_list.p, (int)L.size(), Lcx, r, nullptr, 0, r, Rsm.p, (int64_t)9 * r * r, r3);
+    std::vector<int> cd(T, r);
+    auto set_cdim = [&](int c) {
+        std::vector<int> v(T, c);
+        h_small.alloc(T + 8);
+        int* hp = (int*)h_small.p;
+        for (int i = 0; i < T; ++i) hp[i] = c;
+        HIPCHK(hipMemcpyAsync(cdim.p, hp, sizeof(int) * T, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    };
+    set_cdim(r);
+    RRArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.cdim = cdim.p;
+    ra.r = r;
+    ra.max_sweeps = 40;
+    ra.R = Rsm.p;
+    ra.strideR = (int64_t)9 * r * r;
+    ra.ldR = r3;
+    ra.GX = GX.p;
+    ra.GP = GP.p;
+    ra.strideGX = (int64_t)9 * r * r;
+    ra.ldGX = r3;
+    ra.xi = xi.p;
+    ra.ldxi = r3;
+    ra.status = nullptr;
+    ra.list = d_list.p;
+    launch_rr_hl(ra, (int)L.size(), r, st);
+    {
+        BlockList Ls = bl_empty(n);
+        bl_add(Ls, S.p, sS, n, r, nullptr, 0);
+        gemm_ts(d_list.p, (int)L.size(), Ls, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
+        gemm_ts(d_list.p, (int)L.size(), Lcx, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p, sC, m, m, 1.0,
+                0.0);
+        launch_copy_cols(d_list.p, (int)L.size(), Sn.p, sS, n, S.p, sS, n, n, r, st);
+        launch_copy_cols(d_list.p, (int)L.size(), CSn.p, sC, m, CS.p, sC, m, m, r, st);
+    }
+    auto residual = [&](const int* dl, int nt) {
+        apply(true, dl, nt, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r, d_z.p);
+        launch_resid_xi(dl, nt, Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
+    };
+    residual(d_list.p, (int)L.size());
+    bool hasP = false;
+    const double nC = op.normC;
+    std::vector<double> hz_abs(T, 0.0);
+    {
+        HIPCHK(hipMemcpyAsync(h_z.p, d_z.p, sizeof(zd) * T, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int t = 0; t < T; ++t) hz_abs[t] = sqrt(zabs2(h_z[t]));
+    }
+    const int maxit = P.max_iters;
+    for (int it = 1; it <= maxit && !L.empty(); ++it) {
+        const int nt = (int)L.size();
+        stats.lobpcg_iters += nt;
+        // W <- K^{-1} W (K = I), into S[:, r:2r]
+        launch_copy_cols(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r, st);
+        BlockList Lxp = bl_empty(n);
+        bl_add(Lxp, S.p, sS, n, r, nullptr, 0);
+        if (hasP) bl_add(Lxp, S.p + (size_t)2 * n * r, sS, n, r, nullptr, 0);
+        orthonormalize(L, d_list.p, S.p + (size_t)n * r, sS, n, n, r, &Lxp, hasP ? 2 * r : r,
+                       seed + 1000003ull * it);
+        apply(false, d_list.p, nt, S.p + (size_t)n * r, sS, n, CS.p + (size_t)m * r, sC, m, r, d_z.p);
+        const int c = hasP ? 3 * r : 2 * r;
+        BlockList Lcs = bl_empty(m);
+        bl_add(Lcs, CS.p, sC, m, c, nullptr, 0);
+        r_factor(d_list.p, nt, Lcs, c, nullptr, 0, c, Rsm.p, (int64_t)9 * r * r, r3);
+        set_cdim(c);
+        ra.list = d_list.p;
+        launch_rr_hl(ra, nt, c, st);
+        BlockList Ls = bl_empty(n);
+        bl_add(Ls, S.p, sS, n, c, nullptr, 0);
+        gemm_ts(d_list.p, nt, Ls, c, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
+        gemm_ts(d_list.p, nt, Ls, c, GP.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p + (size_t)n * r, sS, n, n, 1.0,
+                0.0);
+        gemm_ts(d_list.p, nt, Lcs, c, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p, sC, m, m, 1.0, 0.0);
+        gemm_ts(d_list.p, nt, Lcs, c, GP.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p + (size_t)m * r, sC, m, m,
+                1.0, 0.0);
+        launch_copy_cols(d_list.p, nt, Sn.p, sS, n, S.p, sS, n, n, r, st);
+        launch_copy_cols(d_list.p, nt, Sn.p + (size_t)n * r, sS, n, S.p + (size_t)2 * n * r, sS, n, n, r, st);
+        launch_copy_cols(d_list.p, nt, CSn.p, sC, m, CS.p, sC, m, m, r, st);
+        launch_copy_cols(d_list.p, nt, CSn.p + (size_t)m * r, sC, m, CS.p + (size_t)2 * m * r, sC, m, m, r, st);
+        hasP = true;
+        residual(d_list.p, nt);
+        BlockList Lw = bl_empty(n);
+        bl_add(Lw, Wres.p, (int64_t)n * r, n, r, nullptr, 0);
+        colnorm2(d_list.p, nt, Lw, r, nrm2.p, r3);
+        HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_xi.p, xi.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        auto passes = [&](int t) {
+            double nz = nC + hz_abs[t];
+            double x0 = h_xi[(size_t)t * r3];
+            double w0 = sqrt(std::max(0.0, h_nrm2[(size_t)t * r3]));
+            return w0 <= std::max(P.eta_svd * nz * x0, nz * nz * EPSM);
+        };
+        std::vector<int> cand;
+        for (int t : L) if (passes(t)) cand.push_back(t);
+        std::vector<char> fin(T, 0);
+        if (!cand.empty()) {
+            // explicit recomputation of C(z) X before accepting (the implicit
+            // updates of C X drift)
+            upload_list(cand, d_list2);
+            apply(false, d_list2.p, (int)cand.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
+            residual(d_list2.p, (int)cand.size());
+            colnorm2(d_list2.p, (int)cand.size(), Lw, r, nrm2.p, r3);
+            HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int t : cand) if (passes(t)) fin[t] = 1;
+        }
+        std::vector<int> L2;
+        for (int t : L) {
+            if (fin[t]) {
+                sigma[pos[t]] = h_xi[(size_t)t * r3];
+                iters[pos[t]] = it;
+                okv[pos[t]] = 1;
+            } else if (it == maxit) {
+                sigma[pos[t]] = h_xi[(size_t)t * r3];
+                iters[pos[t]] = it;
+                okv[pos[t]] = 0;
+            } else {
+                L2.push_back(t);
+            }
+        }
+        if (L2.size() != L.size()) {
+            L.swap(L2);
+            if (!L.empty()) upload_list(L, d_list);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// R_A = R([W1 W2]) and R_res = R([W3 W4 W5 W6]) of the singular store, with
+// W2 = [V; 0], W5 = W1[:n] and W6 = V because S = [I_n; 0].
+void Engine::refresh_store(const std::vector<int>& L)
+{
+    if (L.empty()) return;
+    upload_list(L, d_list2);
+    const int nt = (int)L.size();
+    BlockList La = bl_empty(m);
+    bl_add(La, sW1.p, (int64_t)m * K, m, 0, d_k.p, 1);
+    bl_add(La, sV.p, (int64_t)n * K, n, 0, d_k.p, 1, n);
+    r_factor(d_list2.p, nt, La, 2 * K, d_k.p, 2, 0, sRA.p, (int64_t)4 * K * K, 2 * K);
+    BlockList Lr = bl_empty(n);
+    bl_add(Lr, sW3.p, (int64_t)n * K, n, 0, d_k.p, 1);
+    bl_add(Lr, sW4.p, (int64_t)n * K, n, 0, d_k.p, 1);
+    bl_add(Lr, sW1.p, (int64_t)m * K, m, 0, d_k.p, 1);
+    bl_add(Lr, sV.p, (int64_t)n * K, n, 0, d_k.p, 1);
+    r_factor(d_list2.p, nt, Lr, 4 * K, d_k.p, 4, 0, sRres.p, (int64_t)16 * K * K, 4 * K);
+}
+

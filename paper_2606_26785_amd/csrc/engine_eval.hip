@@ -1,0 +1,371 @@
+// updateRecy (Alg. 2) for the singular store and the grid-front scheduler.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+void Engine::upload_k()
+{
+    h_small.alloc(T + 8);
+    int* hp = (int*)h_small.p;
+    for (int t = 0; t < T; ++t) hp[t] = tiles[t].k;
+    HIPCHK(hipMemcpyAsync(d_k.p, hp, sizeof(int) * T, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// updateRecy with r_breve = 1 (Alg. 2, Sec. 2.2.2) for every tile in L; the
+// new singular block X (orthonormal, n x r) is S[:, 0:r] of the tile.
+//  1. projection errors rho_j = ||(I - V_j V_j^*) x_1|| of x_1 = X[:, 0] onto
+//     the trailing blocks V_j = [V^{j+1} .. V^p]; l = first j with
+//     rho_j / rho_0 > omega, minus one (eq. (omegaCond)), capped so that at
+//     most k_max / r blocks remain; rho_0 ~ 0 means X is already recycled.
+//     Because V is orthonormal, rho_j^2 = rho_0^2 + ||V_{<j}^* x_1||^2, which
+//     avoids cancellation.
+//  2. block Gram-Schmidt of X against the kept blocks V_l: coefficients U,
+//     new orthonormal block Q with X = V_l U + Q Upp (eq. (blkGS)).
+//  3. the new operator blocks C Q, C^* C Q, C^* S Q (3r column-applies).
+//  4. block unitary rotations restoring the QL form, applied to V and to the
+//     W blocks in one product with the accumulated transform.
+//  5. refresh of the cached R factors.
+void Engine::update_store(const std::vector<int>& Lin)
+{
+    if (Lin.empty()) return;
+    const int64_t sS = (int64_t)n * 3 * r, sX = (int64_t)n * r;
+    const int64_t snk = (int64_t)n * K, smk = (int64_t)m * K;
+    std::vector<int> L = Lin;
+    upload_list(L, d_list2);
+    int nt = (int)L.size();
+    // Xw <- X
+    launch_copy_cols(d_list2.p, nt, S.p, sS, n, Xw.p, sX, n, n, r, st);
+    BlockList Lv = bl_empty(n);
+    bl_add(Lv, sV.p, snk, n, 0, d_k.p, 1);
+    BlockList Lx = bl_empty(n);
+    bl_add(Lx, S.p, sS, n, r, nullptr, 0);
+    BlockList Lxw = bl_empty(n);
+    bl_add(Lxw, Xw.p, sX, n, r, nullptr, 0);
+    // 1. C1 = V^* X, Xw = X - V C1, C2 = V^* Xw, Xw -= V C2
+    gram(d_list2.p, nt, Lv, Lx, K, r, Csm.p, (int64_t)K * 3 * r, K, false, false);
+    gemm_ts(d_list2.p, nt, Lv, K, Csm.p, (int64_t)K * 3 * r, K, nullptr, 0, r, Xw.p, sX, n, n, -1.0, 1.0);
+    gram(d_list2.p, nt, Lv, Lxw, K, r, Ucoef.p, (int64_t)K * r, K, false, false);
+    gemm_ts(d_list2.p, nt, Lv, K, Ucoef.p, (int64_t)K * r, K, nullptr, 0, r, Xw.p, sX, n, n, -1.0, 1.0);
+    colnorm2(d_list2.p, nt, Lxw, r, nrm2.p, 3 * r);
+    h_C.alloc((size_t)T * K * 2 + 8);
+    zd* hc1 = h_C.p;
+    zd* hc2 = h_C.p + (size_t)T * K;
+    for (int t : L) {
+        HIPCHK(hipMemcpyAsync(hc1 + (size_t)t * K, Csm.p + (size_t)t * K * 3 * r, sizeof(zd) * K,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hc2 + (size_t)t * K, Ucoef.p + (size_t)t * K * r, sizeof(zd) * K,
+                              hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * 3 * r, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int pmax = std::max(1, K / r);
+    std::vector<int> Lu;
+    std::vector<int> lsel(T, 0), qsel(T, 0);
+    for (int t : L) {
+        const int p = tiles[t].k / r;
+        const double rho0 = sqrt(std::max(0.0, h_nrm2[(size_t)t * 3 * r]));
+        if (p > 0 && rho0 <= 1e-14) continue;  // x_1 already in the recycled subspace
+        int l = 0;
+        if (p > 0) {
+            int j = 1;
+            double acc = rho0 * rho0;
+            for (j = 1; j <= p; ++j) {
+                // add the coefficients of block j-1 (dropped when the trailing set starts at block j)
+                for (int i = (j - 1) * r; i < j * r; ++i) {
+                    zd c = zadd(hc1[(size_t)t * K + i], hc2[(size_t)t * K + i]);
+                    acc += zabs2(c);
+                }
+                if (sqrt(acc) / rho0 > P.omega) break;
+            }
+            if (j > p) j = p;
+            l = j - 1;
+            if (p - l + 1 > pmax) l = p - pmax + 1;
+            if (l < 0) l = 0;
+        }
+        lsel[t] = l;
+        qsel[t] = p - l;
+        Lu.push_back(t);
+    }
+    if (Lu.empty()) return;
+    L = Lu;
+    nt = (int)L.size();
+    upload_list(L, d_list2);
+    {
+        h_small.alloc(2 * T + 8);
+        int* hl = (int*)h_small.p;
+        for (int t = 0; t < T; ++t) { hl[t] = lsel[t]; hl[T + t] = qsel[t]; }
+        HIPCHK(hipMemcpyAsync(d_l.p, hl, sizeof(int) * T, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_q.p, hl + T, sizeof(int) * T, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    // 2. block Gram-Schmidt against the kept blocks V_l = V[:, l r : p r]
+    BlockList Lvl = bl_empty(n);
+    bl_add(Lvl, sV.p, snk, n, 0, d_q.p, r, 0, d_l.p, r);
+    launch_copy_cols(d_list2.p, nt, S.p, sS, n, Xw.p, sX, n, n, r, st);
+    gram(d_list2.p, nt, Lvl, Lx, K, r, Ucoef.p, (int64_t)K * r, K, false, false);
+    gemm_ts(d_list2.p, nt, Lvl, K, Ucoef.p, (int64_t)K * r, K, nullptr, 0, r, Xw.p, sX, n, n, -1.0, 1.0);
+    orthonormalize(L, d_list2.p, Xw.p, sX, n, n, r, &Lvl, K, P.seed ^ 0xabcdefull ^ (uint64_t)stats.refined);
+    gram(d_list2.p, nt, Lxw, Lx, r, r, Upp.p, (int64_t)r * r, r, false, false);
+    RotArgs ro;
+    memset(&ro, 0, sizeof(ro));
+    ro.list = d_list2.p;
+    ro.qdim = d_q.p;
+    ro.r = r;
+    ro.U = Ucoef.p;
+    ro.strideU = (int64_t)K * r;
+    ro.ldU = K;
+    ro.Upp = Upp.p;
+    ro.strideUpp = (int64_t)r * r;
+    ro.ldUpp = r;
+    ro.Qt = Qt.p;
+    ro.strideQt = (int64_t)K * K;
+    ro.ldQt = K;
+    launch_rotations(ro, nt, pmax - 1, st);
+    // 3. operator blocks of the new basis block (before rotation)
+    const int64_t sT1 = (int64_t)m * 3 * r;
+    launch_zero(Tn1.p, (int64_t)T * sT1, st);
+    launch_copy_cols(d_list2.p, nt, Xw.p, sX, n, Tn1.p + (size_t)m * r, sT1, m, n, r, st);
+    apply(false, d_list2.p, nt, Xw.p, sX, n, Tn1.p, sT1, m, r, nullptr);                 // C Q
+    apply(true, d_list2.p, nt, Tn1.p, sT1, m, Tn2.p, sX, n, r, nullptr);                 // C^* C Q
+    apply(true, d_list2.p, nt, Tn1.p + (size_t)m * r, sT1, m, Tn3.p, sX, n, r, nullptr); // C^* S Q
+    // 4. new k, then [kept | new] Qt for V and each W block
+    for (int t : L) tiles[t].k = (qsel[t] + 1) * r;
+    upload_k();
+    auto rot = [&](zd* src, int64_t srcstride, int64_t srcld, const zd* nb, int64_t nbstride, int64_t nbld,
+                   int64_t rows, zd* dst) {
+        BlockList A = bl_empty(rows);
+        bl_add(A, src, srcstride, srcld, 0, d_q.p, r, 0, d_l.p, r);
+        bl_add(A, nb, nbstride, nbld, r, nullptr, 0);
+        gemm_ts(d_list2.p, nt, A, K, Qt.p, (int64_t)K * K, K, d_k.p, 1, 0, dst, srcstride, srcld, rows, 1.0, 0.0);
+        launch_copy_cols(d_list2.p, nt, dst, srcstride, srcld, src, srcstride, srcld, rows, K, st);
+    };
+    rot(sV.p, snk, n, Xw.p, sX, n, n, uV.p);
+    rot(sW1.p, smk, m, Tn1.p, sT1, m, m, uW1.p);
+    rot(sW3.p, snk, n, Tn2.p, sX, n, n, uW3.p);
+    rot(sW4.p, snk, n, Tn3.p, sX, n, n, uW4.p);
+    // 5. cached R factors
+    refresh_store(L);
+}
+
+// ---------------------------------------------------------------------------
+// Grid-front scheduler.  The grid is cut into tiles; each tile is traversed
+// in batch-zigzag order (Sec. 2.3: bands of height b, columns visited in
+// alternating directions, a snake inside each column batch) and runs the
+// sequential algorithm with its own recycled store, so that every point is
+// tested against the store as updated by all refinements before it in its
+// tile.  One round evaluates the next b points of every tile against its
+// store in one batched launch, accepts the leading run of points that pass,
+// and refines the first rejected point of every tile in one batched
+// LOBPCG-SVD, followed by the batched store updates.
+static void tile_orders(int nx, int ny, int tx, int ty, int b, std::vector<Tile>& tiles)
+{
+    tiles.clear();
+    for (int jy = 0; jy < ty; ++jy) {
+        int y0 = (int)((int64_t)ny * jy / ty), y1 = (int)((int64_t)ny * (jy + 1) / ty);
+        for (int jx = 0; jx < tx; ++jx) {
+            int x0 = (int)((int64_t)nx * jx / tx), x1 = (int)((int64_t)nx * (jx + 1) / tx);
+            Tile t;
+            int band = 0;
+            for (int yb = y0; yb < y1; yb += b, ++band) {
+                int ye = std::min(y1, yb + b);
+                bool ltr = (band % 2 == 0);
+                for (int ci = 0; ci < x1 - x0; ++ci) {
+                    int x = ltr ? (x0 + ci) : (x1 - 1 - ci);
+                    bool up = (ci % 2 == 0);
+                    for (int yi = 0; yi < ye - yb; ++yi) {
+                        int y = up ? (yb + yi) : (ye - 1 - yi);
+                        t.order.push_back(y * nx + x);
+                    }
+                }
+            }
+            if (!t.order.empty()) tiles.push_back(std::move(t));
+        }
+    }
+}
+
+ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* sigma, uint8_t* member,
+                       uint8_t* flags, ps_stats* st_out)
+{
+    auto t_start = std::chrono::steady_clock::now();
+    memset(&stats, 0, sizeof(stats));
+    const int nx = g->nx, ny = g->ny;
+    const int64_t npts = (int64_t)nx * ny;
+    zs.resize(npts);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double x = (nx > 1) ? g->re_lo + (g->re_hi - g->re_lo) * i / (nx - 1) : g->re_lo;
+            double y = (ny > 1) ? g->im_lo + (g->im_hi - g->im_lo) * j / (ny - 1) : g->im_lo;
+            zs[(size_t)j * nx + i] = zmake(x, y);
+        }
+    const int b = std::max(1, P.batch);
+    B = b;
+    int ty = P.tiles_y > 0 ? P.tiles_y : (ny + b - 1) / b;
+    int tx = P.tiles_x > 0 ? P.tiles_x : std::max(1, (int)std::lround(nx / 50.0));
+    ty = std::min(ty, ny);
+    tx = std::min(tx, nx);
+    tile_orders(nx, ny, tx, ty, b, tiles);
+    size_for((int)tiles.size());
+    for (auto& t : tiles) { t.cursor = 0; t.k = 0; }
+    upload_k();
+    std::vector<uint8_t> fl(npts, 0);
+    std::vector<double> sig(npts, 0.0);
+    const double nC = op.normC;
+    bool any_uncert = false;
+    const int64_t sS = (int64_t)n * 3 * r;
+    uint64_t round_seed = P.seed;
+    double t_ritz = 0, t_lob = 0, t_upd = 0;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b2) {
+        return std::chrono::duration<double, std::milli>(b2 - a).count();
+    };
+    while (true) {
+        std::vector<int> active;
+        for (int t = 0; t < T; ++t) if (!tiles[t].done()) active.push_back(t);
+        if (active.empty()) break;
+        stats.rounds++;
+        std::vector<int> R, Rsrc;      // tiles to refine, job index of their Ritz vectors (-1: none)
+        auto t0 = now();
+        if (P.recycle) {
+            // ---- Ritz test of the next window of every tile with a nonempty store
+            std::vector<int> jt;
+            std::vector<int> jp;
+            for (int t : active) {
+                if (tiles[t].k == 0) continue;
+                size_t e = std::min(tiles[t].order.size(), tiles[t].cursor + (size_t)B);
+                for (size_t c = tiles[t].cursor; c < e; ++c) { jt.push_back(t); jp.push_back(tiles[t].order[c]); }
+            }
+            const int nj = (int)jt.size();
+            if (nj > 0) {
+                h_small.alloc((size_t)nj * 2 + 8);
+                h_z.alloc((size_t)nj + T + 8);
+                int* hjt = (int*)h_small.p;
+                double* hn = (double*)(h_small.p + nj);
+                for (int j = 0; j < nj; ++j) {
+                    hjt[j] = jt[j];
+                    h_z[j] = zs[jp[j]];
+                    hn[j] = nC + sqrt(zabs2(zs[jp[j]]));
+                }
+                HIPCHK(hipMemcpyAsync(j_tile.p, hjt, sizeof(int) * nj, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(j_z.p, h_z.p, sizeof(zd) * nj, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(j_nrm.p, hn, sizeof(double) * nj, hipMemcpyHostToDevice, st));
+                RitzArgs ra;
+                memset(&ra, 0, sizeof(ra));
+                ra.njobs = nj;
+                ra.job_tile = j_tile.p;
+                ra.kdim = d_k.p;
+                ra.z = j_z.p;
+                ra.nrm = j_nrm.p;
+                ra.RA = sRA.p;
+                ra.strideRA = (int64_t)4 * K * K;
+                ra.ldRA = 2 * K;
+                ra.Rres = sRres.p;
+                ra.strideRres = (int64_t)16 * K * K;
+                ra.ldRres = 4 * K;
+                ra.nres = 4;
+                ra.nv = 1;
+                ra.ng = r;
+                ra.max_sweeps = 40;
+                ra.mode = 0;
+                ra.eta = P.eta;
+                ra.xi = j_xi.p;
+                ra.res = j_res.p;
+                ra.ldxi = 1;
+                ra.Gout = j_G.p;
+                ra.strideG = (int64_t)K * r;
+                ra.ldG = K;
+                ra.accept = j_acc.p;
+                launch_ritz(ra, K, st);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(h_acc.p, j_acc.p, nj, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(h_xi.p, j_xi.p, sizeof(double) * nj, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+            }
+            int j = 0;
+            for (int t : active) {
+                if (tiles[t].k == 0) { R.push_back(t); Rsrc.push_back(-1); continue; }
+                size_t e = std::min(tiles[t].order.size(), tiles[t].cursor + (size_t)B);
+                size_t w = e - tiles[t].cursor;
+                bool rejected = false;
+                for (size_t c = 0; c < w; ++c, ++j) {
+                    if (rejected) continue;
+                    if (h_acc[j]) {
+                        int pt = tiles[t].order[tiles[t].cursor];
+                        sig[pt] = h_xi[j];
+                        fl[pt] |= PS_FLAG_ACCEPTED;
+                        stats.accepted++;
+                        tiles[t].cursor++;
+                    } else {
+                        rejected = true;
+                        R.push_back(t);
+                        Rsrc.push_back(j);
+                    }
+                }
+            }
+        } else {
+            for (int t : active) { R.push_back(t); Rsrc.push_back(-1); }
+        }
+        auto t1 = now();
+        t_ritz += ms(t0, t1);
+        if (R.empty()) continue;
+        // ---- start blocks: recycled Ritz vectors V g_{1:r}, or seeded random
+        std::vector<int> Rr, Rv;
+        h_small.alloc(T + 8);
+        int* hsrc = (int*)h_small.p;
+        for (size_t i = 0; i < R.size(); ++i) {
+            if (Rsrc[i] < 0) Rr.push_back(R[i]);
+            else { Rv.push_back(R[i]); hsrc[R[i]] = Rsrc[i]; }
+        }
+        if (!Rv.empty()) {
+            HIPCHK(hipMemcpyAsync(d_jobsrc.p, hsrc, sizeof(int) * T, hipMemcpyHostToDevice, st));
+            upload_list(Rv, d_list);
+            launch_gather(d_list.p, (int)Rv.size(), d_jobsrc.p, j_G.p, (int64_t)K * r, X0c.p, (int64_t)K * r,
+                          (int64_t)K * r, st);
+            BlockList Lv = bl_empty(n);
+            bl_add(Lv, sV.p, (int64_t)n * K, n, 0, d_k.p, 1);
+            gemm_ts(d_list.p, (int)Rv.size(), Lv, K, X0c.p, (int64_t)K * r, K, nullptr, 0, r, S.p, sS, n, n, 1.0,
+                    0.0);
+        }
+        if (!Rr.empty()) {
+            upload_list(Rr, d_list);
+            round_seed = round_seed * 6364136223846793005ull + 1442695040888963407ull;
+            launch_randfill(d_list.p, (int)Rr.size(), S.p, sS, n, n, r, nullptr, round_seed, st);
+        }
+        // current z of each refined tile
+        h_z.alloc((size_t)T + 8);
+        for (int t : R) h_z[t] = zs[tiles[t].order[tiles[t].cursor]];
+        HIPCHK(hipMemcpyAsync(d_z.p, h_z.p, sizeof(zd) * T, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<double> sg;
+        std::vector<int> its, okv;
+        lobpcg(R, sg, its, okv, round_seed ^ 0x9e3779b97f4a7c15ull);
+        auto t2 = now();
+        t_lob += ms(t1, t2);
+        for (size_t i = 0; i < R.size(); ++i) {
+            int t = R[i];
+            int pt = tiles[t].order[tiles[t].cursor];
+            sig[pt] = sg[i];
+            fl[pt] |= PS_FLAG_REFINED;
+            if (!okv[i]) { fl[pt] |= PS_FLAG_UNCERTIFIED; any_uncert = true; stats.uncertified++; }
+            stats.refined++;
+            tiles[t].cursor++;
+        }
+        if (P.recycle) update_store(R);
+        t_upd += ms(t2, now());
+    }
+    stats.points = npts;
+    for (int64_t p = 0; p < npts; ++p) sigma[p] = sig[p];
+    if (flags) memcpy(flags, fl.data(), npts);
+    if (member)
+        for (int e = 0; e < n_eps; ++e)
+            for (int64_t p = 0; p < npts; ++p) member[(size_t)e * npts + p] = (uint8_t)(sig[p] < eps[e]);
+    stats.t_ritz_ms = t_ritz;
+    stats.t_lobpcg_ms = t_lob;
+    stats.t_update_ms = t_upd;
+    stats.t_total_ms = ms(t_start, now());
+    if (st_out) *st_out = stats;
+    return any_uncert ? PS_WARN_UNCERTIFIED : PS_OK;
+}

@@ -1,0 +1,165 @@
+// Operator applies C X and C^* Y for the column blocks of many tiles at once.
+//
+// Dense C: complex GEMM on the FP64 matrix cores.  The complex product is
+// split into four real products accumulated into two 16 x 16 accumulators
+// (re += Ar Xr - Ai Xi, im += Ar Xi + Ai Xr) with v_mfma_f64_16x16x4f64.
+// Tiles of A (64 x 32) and X (32 x 32) are staged through LDS.  K is split
+// over workgroups so that narrow right-hand sides still fill all 256 CUs; a
+// second pass sums the partials and applies the shift epilogue
+//   Y[:n] -= z X[:n]          (C(z) X = C X - z S X, S = [I_n; 0]), or
+//   Y     -= conj(z) X[:n]    (C(z)^* Y = C^* Y - conj(z) S^* Y).
+// Sparse C: CSR, one thread per (row, tile), looping over the w columns.
+#include "zdev.h"
+#include "kernels.h"
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+#define BM 64
+#define BN 32
+#define BK 32
+#define NT 256
+
+__global__ void __launch_bounds__(NT) k_dense_gemm(DenseApplyArgs a, int64_t kchunk)
+{
+    __shared__ zd As[BK][BM + 1];
+    __shared__ zd Xs[BK][BN + 1];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t i0 = (int64_t)blockIdx.x * BM;
+    const int j0 = blockIdx.y * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    int64_t kend = kbeg + kchunk;
+    if (kend > a.K) kend = a.K;
+    const int N = a.ntiles * a.w;
+
+    // this thread's X column for staging loads: column jl = tid % BN, rows tid / BN + 8 q
+    const int jl = tid % BN;
+    const int gc = j0 + jl;
+    const zd* xcol = nullptr;
+    if (gc < N) {
+        int t = gc / a.w, j = gc - t * a.w;
+        xcol = a.X + (size_t)a.list[t] * a.xstride + (size_t)j * a.ldx;
+    }
+    dvec4 acc_re[2], acc_im[2];
+    for (int c = 0; c < 2; ++c) {
+        acc_re[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
+        acc_im[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
+    }
+    const int mrow = lane & 15;     // row within a 16-row block (A operand) / column (B operand)
+    const int kq = lane >> 4;       // k index within the 4-wide step
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        // stage A[i0 : i0+64, k0 : k0+32] as As[k][i]
+        for (int e = tid; e < BM * BK; e += NT) {
+            int ii = e % BM, kk = e / BM;
+            int64_t gi = i0 + ii, gk = k0 + kk;
+            As[kk][ii] = (gi < a.m && gk < kend) ? a.A[gi + gk * a.lda] : zmake(0.0, 0.0);
+        }
+        // stage X[k0 : k0+32, j0 : j0+32] as Xs[k][j]
+        for (int kk = tid / BN; kk < BK; kk += NT / BN) {
+            int64_t gk = k0 + kk;
+            Xs[kk][jl] = (xcol && gk < kend) ? xcol[gk] : zmake(0.0, 0.0);
+        }
+        __syncthreads();
+        // wave w: rows 16 w .. 16 w + 15 of the 64-row tile, columns 0..31 (2 blocks)
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            zd av = As[ks + kq][wave * 16 + mrow];
+            double ar = av.x, ai = av.y, nai = -av.y;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                zd xv = Xs[ks + kq][cb * 16 + mrow];
+                acc_re[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xv.x, acc_re[cb], 0, 0, 0);
+                acc_re[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, xv.y, acc_re[cb], 0, 0, 0);
+                acc_im[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xv.y, acc_im[cb], 0, 0, 0);
+                acc_im[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xv.x, acc_im[cb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D layout of v_mfma_f64_16x16x4f64: lane l, element v -> row (l / 16) + 4 v, column l % 16
+    zd* part = a.part + (size_t)blockIdx.z * (size_t)a.m * N;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        int col = j0 + cb * 16 + (lane & 15);
+        if (col >= N) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int64_t row = i0 + wave * 16 + (lane >> 4) + 4 * v;
+            if (row < a.m) part[row + (size_t)col * a.m] = zmake(acc_re[cb][v], acc_im[cb][v]);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_dense_reduce(DenseApplyArgs a)
+{
+    const int N = a.ntiles * a.w;
+    int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= a.m * N) return;
+    int64_t row = e % a.m;
+    int col = (int)(e / a.m);
+    zd s = zmake(0.0, 0.0);
+    for (int z = 0; z < a.splitk; ++z) s = zadd(s, a.part[(size_t)z * a.m * N + e]);
+    int t = col / a.w, j = col - t * a.w;
+    int tile = a.list[t];
+    if (a.z && row < a.nshift) {
+        zd zz = a.z[tile];
+        if (a.conjz) zz.y = -zz.y;
+        zd x = a.X[(size_t)tile * a.xstride + row + (size_t)j * a.ldx];
+        s = zsub(s, zmul(zz, x));
+    }
+    a.Y[(size_t)tile * a.ystride + row + (size_t)j * a.ldy] = s;
+}
+
+size_t dense_apply_part_bytes(int64_t m, int maxcols, int splitk)
+{
+    return (size_t)m * maxcols * splitk * sizeof(zd);
+}
+
+void launch_dense_apply(DenseApplyArgs& a, hipStream_t s)
+{
+    if (a.ntiles <= 0) return;
+    const int N = a.ntiles * a.w;
+    int64_t mb = (a.m + BM - 1) / BM;
+    int nbk = (N + BN - 1) / BN;
+    // enough workgroups to fill the chip: aim for ~2048
+    int64_t base = mb * nbk;
+    int sk = (int)((2048 + base - 1) / base);
+    int64_t maxsk = (a.K + BK * 4 - 1) / (BK * 4);
+    if (sk > maxsk) sk = (int)maxsk;
+    if (sk > a.splitk) sk = a.splitk;   // a.splitk carries the workspace capacity
+    if (sk < 1) sk = 1;
+    int64_t kchunk = (a.K + sk - 1) / sk;
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    sk = (int)((a.K + kchunk - 1) / kchunk);
+    a.splitk = sk;
+    hipLaunchKernelGGL(k_dense_gemm, dim3((unsigned)mb, nbk, sk), dim3(NT), 0, s, a, kchunk);
+    int64_t tot = a.m * N;
+    hipLaunchKernelGGL(k_dense_reduce, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_csr_apply(CsrApplyArgs a)
+{
+    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (row >= a.m) return;
+    const int tile = a.list[blockIdx.y];
+    const int64_t b = a.rowptr[row], e = a.rowptr[row + 1];
+    const zd* X = a.X + (size_t)tile * a.xstride;
+    zd* Y = a.Y + (size_t)tile * a.ystride;
+    zd zz = zmake(0.0, 0.0);
+    if (a.z) { zz = a.z[tile]; if (a.conjz) zz.y = -zz.y; }
+    for (int j = 0; j < a.w; ++j) {
+        const zd* xc = X + (size_t)j * a.ldx;
+        zd s = zmake(0.0, 0.0);
+        for (int64_t p = b; p < e; ++p) zfma(s, a.vals[p], xc[a.colind[p]]);
+        if (a.z && row < a.nshift) s = zsub(s, zmul(zz, xc[row]));
+        Y[row + (size_t)j * a.ldy] = s;
+    }
+}
+
+void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s)
+{
+    if (a.ntiles <= 0) return;
+    dim3 g((unsigned)((a.m + NT - 1) / NT), a.ntiles);
+    hipLaunchKernelGGL(k_csr_apply, g, dim3(NT), 0, s, a);
+}

@@ -1,0 +1,358 @@
+// Tall-skinny batched kernels: Gram matrices (double or double-double
+// accumulation), products with small matrices, column norms and the
+// elementwise epilogues of LOBPCG-SVD.  All are HBM-bandwidth kernels; one
+// launch covers every active tile.
+#include "zdev.h"
+#include "kernels.h"
+
+#define NT 256
+
+// column count of block b for tile t
+__device__ __host__ inline int bl_cols(const BlockList& L, int b, int t)
+{
+    return L.dims[b] ? L.dims[b][t] * L.mul[b] : L.ncols[b];
+}
+// element (i, c) of the block list for tile t (zero beyond a block's rows)
+__device__ inline zd bl_get(const BlockList& L, int t, int64_t i, int c)
+{
+    for (int b = 0; b < L.nb; ++b) {
+        int nc = bl_cols(L, b, t);
+        if (c < nc) {
+            int64_t br = L.brows[b] ? L.brows[b] : L.rows;
+            if (i >= br) return zmake(0.0, 0.0);
+            int c0 = L.coff[b] ? L.coff[b][t] * L.coffmul[b] : 0;
+            return L.ptr[b][(size_t)t * L.stride[b] + i + (size_t)(c + c0) * L.ld[b]];
+        }
+        c -= nc;
+    }
+    return zmake(0.0, 0.0);
+}
+__device__ inline int bl_total(const BlockList& L, int t)
+{
+    int s = 0;
+    for (int b = 0; b < L.nb; ++b) s += bl_cols(L, b, t);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Gram: part[(tile, chunk)] = A[rows of chunk]^* B[rows of chunk] for one
+// 32 x 32 output tile per workgroup (grid: chunks x out-tiles x tiles).
+template <int DD>
+__global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
+{
+    __shared__ zd As[32][33];
+    __shared__ zd Bs[32][33];
+    const int chunk = blockIdx.x;
+    const int ot = blockIdx.y;
+    const int ti = ot / ntj, tj = ot % ntj;
+    const int tix = blockIdx.z;
+    const int tile = a.list[tix];
+    const int ca = bl_total(a.A, tile), cb = bl_total(a.B, tile);
+    if (ti * 32 >= ca || tj * 32 >= cb) return;
+    if (a.hermitian_upper_only && tj < ti) return;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)chunk * a.chunk_rows;
+    int64_t r1 = r0 + a.chunk_rows;
+    if (r1 > a.A.rows) r1 = a.A.rows;
+    const int li = tid & 31, lj0 = tid >> 5;   // outputs (li, lj0 + 8 q)
+    zacc acc[4];
+    zd accd[4];
+    for (int q = 0; q < 4; ++q) { zacc_init(acc[q]); accd[q] = zmake(0.0, 0.0); }
+    for (int64_t rb = r0; rb < r1; rb += 32) {
+        // stage 32 rows x 32 columns of A and B
+        for (int e = tid; e < 32 * 32; e += NT) {
+            int rr = e & 31, cc = e >> 5;
+            int64_t i = rb + rr;
+            int ga = ti * 32 + cc, gb = tj * 32 + cc;
+            As[rr][cc] = (i < r1 && ga < ca) ? bl_get(a.A, tile, i, ga) : zmake(0.0, 0.0);
+            Bs[rr][cc] = (i < r1 && gb < cb) ? bl_get(a.B, tile, i, gb) : zmake(0.0, 0.0);
+        }
+        __syncthreads();
+        int nr = (int)((r1 - rb) < 32 ? (r1 - rb) : 32);
+        for (int rr = 0; rr < nr; ++rr) {
+            zd x = As[rr][li];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                zd y = Bs[rr][lj0 + 8 * q];
+                if (DD) zacc_cfma(acc[q], x, y);
+                else zcfma(accd[q], x, y);
+            }
+        }
+        __syncthreads();
+    }
+    const size_t base = ((size_t)tix * a.nchunks + chunk) * a.part_stride;
+    for (int q = 0; q < 4; ++q) {
+        int gi = ti * 32 + li, gj = tj * 32 + lj0 + 8 * q;
+        if (gi < ca && gj < cb) {
+            size_t off = base + gi + (size_t)gj * a.camax;
+            if (DD) ((zdd*)a.part)[off] = zacc_value(acc[q]);
+            else ((zd*)a.part)[off] = accd[q];
+        }
+    }
+}
+
+template <int DD>
+__global__ void __launch_bounds__(NT) k_gram_reduce(GramArgs a)
+{
+    const int tix = blockIdx.y;
+    const int tile = a.list[tix];
+    const int ca = bl_total(a.A, tile), cb = bl_total(a.B, tile);
+    int e = blockIdx.x * NT + threadIdx.x;
+    if (e >= ca * cb) return;
+    int gi = e % ca, gj = e / ca;
+    if (a.hermitian_upper_only && (gj / 32) < (gi / 32)) return;
+    const size_t base = (size_t)tix * a.nchunks * a.part_stride + gi + (size_t)gj * a.camax;
+    if (DD) {
+        zdd s = zdd_zero();
+        for (int c = 0; c < a.nchunks; ++c) {
+            int64_t r0 = (int64_t)c * a.chunk_rows;
+            if (r0 >= a.A.rows) break;
+            s = zdd_add(s, ((const zdd*)a.part)[base + (size_t)c * a.part_stride]);
+        }
+        ((zdd*)a.out)[(size_t)tile * a.strideOut + gi + (size_t)gj * a.ldOut] = s;
+    } else {
+        zd s = zmake(0.0, 0.0);
+        for (int c = 0; c < a.nchunks; ++c) {
+            int64_t r0 = (int64_t)c * a.chunk_rows;
+            if (r0 >= a.A.rows) break;
+            s = zadd(s, ((const zd*)a.part)[base + (size_t)c * a.part_stride]);
+        }
+        ((zd*)a.out)[(size_t)tile * a.strideOut + gi + (size_t)gj * a.ldOut] = s;
+    }
+}
+
+size_t gram_part_bytes(int64_t rows, int camax, int cbmax, int ntiles, int dd, int chunk_rows)
+{
+    int64_t nch = (rows + chunk_rows - 1) / chunk_rows;
+    return (size_t)ntiles * nch * camax * cbmax * (dd ? sizeof(zdd) : sizeof(zd));
+}
+
+void launch_gram(GramArgs& a, hipStream_t s)
+{
+    if (a.ntiles <= 0) return;
+    a.nchunks = (int)((a.A.rows + a.chunk_rows - 1) / a.chunk_rows);
+    a.part_stride = (int64_t)a.camax * a.cbmax;
+    int nti = (a.camax + 31) / 32, ntj = (a.cbmax + 31) / 32;
+    dim3 g1(a.nchunks, nti * ntj, a.ntiles);
+    dim3 g2((a.camax * a.cbmax + NT - 1) / NT, a.ntiles);
+    if (a.dd) {
+        hipLaunchKernelGGL(k_gram_part<1>, g1, dim3(NT), 0, s, a, ntj);
+        hipLaunchKernelGGL(k_gram_reduce<1>, g2, dim3(NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_gram_part<0>, g1, dim3(NT), 0, s, a, ntj);
+        hipLaunchKernelGGL(k_gram_reduce<0>, g2, dim3(NT), 0, s, a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y[:, chunk] = A G[:, chunk] (+ Y if beta == 1): one row per thread,
+// 16 output columns per workgroup column (grid: rowblocks x colchunks x tiles)
+#define TSC 16
+__global__ void __launch_bounds__(NT) k_gemm_ts(GemmTSArgs a)
+{
+    extern __shared__ double smem_d[];
+    zd* Gs = (zd*)smem_d;   // camax x TSC
+    const int tix = blockIdx.z;
+    const int tile = a.list[tix];
+    const int ca = bl_total(a.A, tile);
+    const int cb = a.cbdims ? a.cbdims[tile] * a.cbmul : a.cb;
+    const int c0 = blockIdx.y * TSC;
+    if (c0 >= cb) return;
+    const int nc = min(TSC, cb - c0);
+    const zd* G = a.G + (size_t)tile * a.strideG;
+    for (int e = threadIdx.x; e < ca * TSC; e += NT) {
+        int i = e % ca, j = e / ca;
+        Gs[i + j * ca] = (j < nc) ? G[i + (size_t)(c0 + j) * a.ldG] : zmake(0.0, 0.0);
+    }
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (row >= a.rows) return;
+    zd acc[TSC];
+#pragma unroll
+    for (int j = 0; j < TSC; ++j) acc[j] = zmake(0.0, 0.0);
+    int cglob = 0;
+    for (int b = 0; b < a.A.nb; ++b) {
+        int ncb = bl_cols(a.A, b, tile);
+        int64_t br = a.A.brows[b] ? a.A.brows[b] : a.A.rows;
+        if (row < br) {
+            int cof = a.A.coff[b] ? a.A.coff[b][tile] * a.A.coffmul[b] : 0;
+            const zd* p = a.A.ptr[b] + (size_t)tile * a.A.stride[b] + (size_t)cof * a.A.ld[b] + row;
+            for (int c = 0; c < ncb; ++c) {
+                zd x = p[(size_t)c * a.A.ld[b]];
+                const zd* gr = Gs + (cglob + c);
+#pragma unroll
+                for (int j = 0; j < TSC; ++j) zfma(acc[j], x, gr[j * ca]);
+            }
+        }
+        cglob += ncb;
+    }
+    zd* Y = a.Y + (size_t)tile * a.strideY + row;
+#pragma unroll
+    for (int j = 0; j < TSC; ++j) {
+        if (j < nc) {
+            zd v = zscale(acc[j], a.alpha);
+            if (a.beta != 0.0) v = zadd(v, Y[(size_t)(c0 + j) * a.ldY]);
+            Y[(size_t)(c0 + j) * a.ldY] = v;
+        }
+    }
+}
+
+void launch_gemm_ts(const GemmTSArgs& a, hipStream_t s)
+{
+    if (a.ntiles <= 0 || a.rows <= 0) return;
+    dim3 g((unsigned)((a.rows + NT - 1) / NT), (a.cbmax + TSC - 1) / TSC, a.ntiles);
+    size_t sm = (size_t)a.camax * TSC * sizeof(zd);
+    hipLaunchKernelGGL(k_gemm_ts, g, dim3(NT), sm, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// column squared norms: partials per chunk, then reduce
+__global__ void __launch_bounds__(NT) k_colnorm_part(NormArgs a)
+{
+    const int chunk = blockIdx.x;
+    const int tix = blockIdx.y;
+    const int tile = a.list[tix];
+    const int ca = bl_total(a.A, tile);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r0 = (int64_t)chunk * a.chunk_rows;
+    int64_t r1 = r0 + a.chunk_rows;
+    if (r1 > a.A.rows) r1 = a.A.rows;
+    for (int c = w; c < ca; c += NT / 64) {
+        double s = 0;
+        for (int64_t i = r0 + lane; i < r1; i += 64) s += zabs2(bl_get(a.A, tile, i, c));
+        s = wave_sum(s);
+        if (lane == 0) a.part[((size_t)tix * a.nchunks + chunk) * a.camax + c] = s;
+    }
+}
+__global__ void k_colnorm_reduce(NormArgs a)
+{
+    const int tix = blockIdx.x;
+    const int tile = a.list[tix];
+    const int ca = bl_total(a.A, tile);
+    for (int c = threadIdx.x; c < ca; c += blockDim.x) {
+        double s = 0;
+        for (int ch = 0; ch < a.nchunks; ++ch) s += a.part[((size_t)tix * a.nchunks + ch) * a.camax + c];
+        a.out[(size_t)tile * a.ldo + c] = s;
+    }
+}
+void launch_colnorm2(NormArgs& a, hipStream_t s)
+{
+    if (a.ntiles <= 0) return;
+    a.nchunks = (int)((a.A.rows + a.chunk_rows - 1) / a.chunk_rows);
+    hipLaunchKernelGGL(k_colnorm_part, dim3(a.nchunks, a.ntiles), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL(k_colnorm_reduce, dim3(a.ntiles), dim3(64), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+__global__ void k_copy_cols(const int* list, const zd* src, int64_t sstride, int64_t lds, zd* dst,
+                            int64_t dstride, int64_t ldd, int64_t rows, int cols)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    int64_t i = e % rows, j = e / rows;
+    dst[(size_t)tile * dstride + i + j * ldd] = src[(size_t)tile * sstride + i + j * lds];
+}
+void launch_copy_cols(const int* list, int ntiles, const zd* src, int64_t sstride, int64_t lds, zd* dst,
+                      int64_t dstride, int64_t ldd, int64_t rows, int cols, hipStream_t s)
+{
+    if (ntiles <= 0 || rows * cols == 0) return;
+    dim3 g((unsigned)((rows * cols + NT - 1) / NT), ntiles);
+    hipLaunchKernelGGL(k_copy_cols, g, dim3(NT), 0, s, list, src, sstride, lds, dst, dstride, ldd, rows, cols);
+}
+
+__global__ void k_scale_cols(const int* list, zd* A, int64_t stride, int64_t lda, int64_t rows, int cols,
+                             const double* d, int ldd, int invert)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    int64_t i = e % rows, j = e / rows;
+    double v = d[(size_t)tile * ldd + j];
+    double f = invert ? (v > 0.0 ? 1.0 / v : 0.0) : v;
+    zd* p = A + (size_t)tile * stride + i + j * lda;
+    *p = zscale(*p, f);
+}
+void launch_scale_cols(const int* list, int ntiles, zd* A, int64_t stride, int64_t lda, int64_t rows, int cols,
+                       const double* d, int ldd, int invert, hipStream_t s)
+{
+    if (ntiles <= 0 || rows * cols == 0) return;
+    dim3 g((unsigned)((rows * cols + NT - 1) / NT), ntiles);
+    hipLaunchKernelGGL(k_scale_cols, g, dim3(NT), 0, s, list, A, stride, lda, rows, cols, d, ldd, invert);
+}
+
+__global__ void k_zaxpy_tile(const int* list, const zd* z, int conjz, zd* Y, int64_t ystride, int64_t ldy,
+                             const zd* X, int64_t xstride, int64_t ldx, int64_t rows, int cols)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    int64_t i = e % rows, j = e / rows;
+    zd zz = z[tile];
+    if (conjz) zz.y = -zz.y;
+    zd* y = Y + (size_t)tile * ystride + i + j * ldy;
+    zd x = X[(size_t)tile * xstride + i + j * ldx];
+    *y = zsub(*y, zmul(zz, x));
+}
+void launch_zaxpy_tile(const int* list, int ntiles, const zd* z, int conjz, zd* Y, int64_t ystride, int64_t ldy,
+                       const zd* X, int64_t xstride, int64_t ldx, int64_t rows, int cols, hipStream_t s)
+{
+    if (ntiles <= 0 || rows * cols == 0) return;
+    dim3 g((unsigned)((rows * cols + NT - 1) / NT), ntiles);
+    hipLaunchKernelGGL(k_zaxpy_tile, g, dim3(NT), 0, s, list, z, conjz, Y, ystride, ldy, X, xstride, ldx, rows, cols);
+}
+
+__global__ void k_resid_xi(const int* list, zd* Y, int64_t ystride, int64_t ldy, const zd* X, int64_t xstride,
+                           int64_t ldx, const double* xi, int ldxi, int64_t rows, int cols)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    int64_t i = e % rows, j = e / rows;
+    double x2 = xi[(size_t)tile * ldxi + j];
+    x2 *= x2;
+    zd* y = Y + (size_t)tile * ystride + i + j * ldy;
+    zd x = X[(size_t)tile * xstride + i + j * ldx];
+    *y = zmake(y->x - x2 * x.x, y->y - x2 * x.y);
+}
+void launch_resid_xi(const int* list, int ntiles, zd* Y, int64_t ystride, int64_t ldy, const zd* X, int64_t xstride,
+                     int64_t ldx, const double* xi, int ldxi, int64_t rows, int cols, hipStream_t s)
+{
+    if (ntiles <= 0 || rows * cols == 0) return;
+    dim3 g((unsigned)((rows * cols + NT - 1) / NT), ntiles);
+    hipLaunchKernelGGL(k_resid_xi, g, dim3(NT), 0, s, list, Y, ystride, ldy, X, xstride, ldx, xi, ldxi, rows, cols);
+}
+
+__global__ void k_randfill(const int* list, zd* A, int64_t stride, int64_t lda, int64_t rows, int cols,
+                           const uint32_t* mask, uint64_t seed)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    int64_t i = e % rows, j = e / rows;
+    if (mask && !((mask[tile] >> j) & 1u)) return;
+    uint64_t key = seed ^ ((uint64_t)tile << 48) ^ ((uint64_t)j << 40) ^ (uint64_t)i;
+    // Box-Muller on two uniforms
+    double u1 = u01(key * 2 + 1), u2 = u01(key * 2 + 2);
+    double rad = sqrt(-2.0 * log(u1)) * 0.7071067811865476;
+    A[(size_t)tile * stride + i + j * lda] = zmake(rad * cos(6.283185307179586 * u2), rad * sin(6.283185307179586 * u2));
+}
+void launch_randfill(const int* list, int ntiles, zd* A, int64_t stride, int64_t lda, int64_t rows, int cols,
+                     const uint32_t* mask, uint64_t seed, hipStream_t s)
+{
+    if (ntiles <= 0 || rows * cols == 0) return;
+    dim3 g((unsigned)((rows * cols + NT - 1) / NT), ntiles);
+    hipLaunchKernelGGL(k_randfill, g, dim3(NT), 0, s, list, A, stride, lda, rows, cols, mask, seed);
+}
+
+__global__ void k_zero(zd* A, int64_t count)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) A[e] = zmake(0.0, 0.0);
+}
+void launch_zero(zd* A, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, s, A, count);
+}

@@ -1,0 +1,191 @@
+// C ABI (include/ps.h): argument checking, handle lifecycle, error mapping.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "engine.h"
+
+struct ps_matrix {
+    Engine eng;
+};
+
+static thread_local std::string g_last_error;
+
+static ps_status fail(ps_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+extern "C" {
+
+void ps_default_params(ps_params* p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->r = 8;
+    p->k_max = 32;
+    p->rbar = 16;
+    p->kbar_max = 64;
+    p->max_iters = 300;
+    p->precond = 0;
+    p->tiles_x = 0;
+    p->tiles_y = 0;
+    p->batch = 20;
+    p->recycle = 1;
+    p->eta = 1e-6;
+    p->eta_svd = 1e-9;
+    p->eta_proj = 1e-4;
+    p->omega = 1.6;
+    p->tau_min = 1e-3;
+    p->tau_max = 30.0;
+    p->zdag_re = NAN;
+    p->zdag_im = NAN;
+    p->seed = 20261203ull;
+}
+
+const char* ps_strerror(ps_status s)
+{
+    switch (s) {
+    case PS_OK: return "ok";
+    case PS_WARN_UNCERTIFIED: return "some points hit the LOBPCG iteration cap";
+    case PS_EINVAL: return "invalid argument";
+    case PS_ENOMEM: return "out of device memory";
+    case PS_EDEVICE: return "HIP device error";
+    case PS_EBREAKDOWN: return "numerical breakdown";
+    case PS_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_stream, ps_matrix** out)
+{
+    if (!d || !out) return fail(PS_EINVAL, "NULL descriptor or output handle");
+    *out = nullptr;
+    ps_params p;
+    if (params) p = *params; else ps_default_params(&p);
+    if (d->m < d->n || d->n < 1) return fail(PS_EINVAL, "need m >= n >= 1");
+    if (d->m > ((int64_t)1 << 31) - 1) return fail(PS_EINVAL, "m too large for int32 column indices");
+    if (d->kind == PS_DENSE) {
+        if (!d->dense || d->ld < d->m) return fail(PS_EINVAL, "dense: NULL data or ld < m");
+    } else if (d->kind == PS_CSR) {
+        if (!d->rowptr || !d->colind || !d->vals || d->nnz < 0) return fail(PS_EINVAL, "CSR: NULL arrays");
+    } else {
+        return fail(PS_EINVAL, "unknown matrix kind");
+    }
+    if (p.r < 2 || p.r > 16 || (p.r & 1)) return fail(PS_EINVAL, "r must be even, 2..16");
+    if (p.k_max < p.r || p.k_max % p.r || p.k_max > 64) return fail(PS_EINVAL, "k_max must be a multiple of r, <= 64");
+    if (p.rbar < 2 || p.rbar > 16 || (p.rbar & 1)) return fail(PS_EINVAL, "rbar must be even, 2..16");
+    if (p.kbar_max < p.rbar || p.kbar_max % p.rbar || p.kbar_max > 64)
+        return fail(PS_EINVAL, "kbar_max must be a multiple of rbar, <= 64");
+    if (p.max_iters < 1 || p.batch < 1) return fail(PS_EINVAL, "max_iters and batch must be positive");
+    if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0)) return fail(PS_EINVAL, "bad tolerances");
+    if (p.precond != 0) return fail(PS_EUNSUPPORTED, "precond != 0 is not available in this build");
+    if (d->kind == PS_DENSE && !d->on_device) {
+        for (int64_t j = 0; j < d->n; ++j)
+            for (int64_t i = 0; i < 2 * d->m; ++i)
+                if (!std::isfinite(d->dense[2 * d->ld * j + i])) return fail(PS_EINVAL, "non-finite entry");
+    }
+    ps_matrix* h = new (std::nothrow) ps_matrix();
+    if (!h) return fail(PS_ENOMEM, "host allocation failed");
+    try {
+        h->eng.create(d, &p, (hipStream_t)hip_stream);
+    } catch (const InvalidArg& e) {
+        delete h;
+        return fail(PS_EINVAL, e.what());
+    } catch (const DeviceError& e) {
+        delete h;
+        std::string w = e.what();
+        return fail(w.find("out of memory") != std::string::npos ? PS_ENOMEM : PS_EDEVICE, w);
+    } catch (const std::bad_alloc&) {
+        delete h;
+        return fail(PS_ENOMEM, "host allocation failed");
+    }
+    *out = h;
+    return PS_OK;
+}
+
+ps_status ps_grid(double re_lo, double re_hi, double im_lo, double im_hi, int32_t nx, int32_t ny, ps_gridh** out)
+{
+    if (!out) return fail(PS_EINVAL, "NULL output handle");
+    *out = nullptr;
+    if (nx < 1 || ny < 1) return fail(PS_EINVAL, "nx and ny must be >= 1");
+    if (!std::isfinite(re_lo) || !std::isfinite(re_hi) || !std::isfinite(im_lo) || !std::isfinite(im_hi))
+        return fail(PS_EINVAL, "non-finite region");
+    ps_gridh* g = new (std::nothrow) ps_gridh();
+    if (!g) return fail(PS_ENOMEM, "host allocation failed");
+    g->re_lo = re_lo;
+    g->re_hi = re_hi;
+    g->im_lo = im_lo;
+    g->im_hi = im_hi;
+    g->nx = nx;
+    g->ny = ny;
+    *out = g;
+    return PS_OK;
+}
+
+ps_status ps_eval(ps_matrix* h, const ps_gridh* g, const double* eps, int32_t n_eps, double* sigma,
+                  uint8_t* member, uint8_t* flags, ps_stats* stats)
+{
+    if (!h || !g || !sigma) return fail(PS_EINVAL, "NULL handle, grid or sigma");
+    if (n_eps < 0 || (n_eps > 0 && !eps)) return fail(PS_EINVAL, "bad eps list");
+    if (n_eps > 0 && !member) return fail(PS_EINVAL, "member output required when n_eps > 0");
+    try {
+        return h->eng.eval(g, eps, n_eps, sigma, member, flags, stats);
+    } catch (const InvalidArg& e) {
+        return fail(PS_EINVAL, e.what());
+    } catch (const DeviceError& e) {
+        std::string w = e.what();
+        return fail(w.find("out of memory") != std::string::npos ? PS_ENOMEM : PS_EDEVICE, w);
+    } catch (const std::bad_alloc&) {
+        return fail(PS_ENOMEM, "host allocation failed");
+    }
+}
+
+void ps_grid_destroy(ps_gridh* g) { delete g; }
+
+void ps_destroy(ps_matrix* h)
+{
+    if (!h) return;
+    if (h->eng.st) (void)hipStreamSynchronize(h->eng.st);
+    else (void)hipDeviceSynchronize();
+    delete h;
+}
+
+}  // extern "C"
+
+#include "../../include/ps_debug.h"
+
+extern "C" ps_status ps_debug_apply(ps_matrix* h, int32_t herm, double z_re, double z_im, const double* X,
+                                    int32_t w, double* Y)
+{
+    if (!h || !X || !Y) return fail(PS_EINVAL, "NULL argument");
+    if (w < 1 || w > 64) return fail(PS_EINVAL, "w must be 1..64");
+    try {
+        Engine& E = h->eng;
+        int64_t rin = herm ? E.m : E.n, rout = herm ? E.n : E.m;
+        DBuf<zd> dX, dY;
+        DBuf<int> dl;
+        DBuf<zd> dz;
+        dX.alloc((size_t)rin * w);
+        dY.alloc((size_t)rout * w);
+        dl.alloc(1);
+        dz.alloc(1);
+        int zero = 0;
+        zd zz = zmake(z_re, z_im);
+        HIPCHK(hipMemcpy(dl.p, &zero, sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dz.p, &zz, sizeof(zd), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dX.p, X, sizeof(zd) * rin * w, hipMemcpyHostToDevice));
+        E.apply(herm != 0, dl.p, 1, dX.p, 0, rin, dY.p, 0, rout, w, dz.p);
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(Y, dY.p, sizeof(zd) * rout * w, hipMemcpyDeviceToHost));
+        return PS_OK;
+    } catch (const std::exception& e) {
+        return fail(PS_EDEVICE, e.what());
+    }
+}
+
+extern "C" double ps_debug_norm(const ps_matrix* h) { return h ? h->eng.op.normC : 0.0; }
