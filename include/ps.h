@@ -81,8 +81,11 @@ typedef struct {
     int32_t rbar;       /* projection block size rbar (default 16) */
     int32_t kbar_max;   /* cap on the recycled projection dimension (default 64) */
     int32_t max_iters;  /* LOBPCG iteration cap (default 300) */
-    int32_t precond;    /* 0: K = I; 1: two-level K_E with recycled projection
-                           subspace on a base preconditioner (default 1) */
+    int32_t precond;    /* LOBPCG preconditioner K (Sec. 3): 0: K = I;
+                           1: base preconditioner K = F^* F ~ N(z_dag), rebuilt
+                           by the rule of eq. (tauRecycle) (dense C: F is the
+                           Cholesky factor of N(z_dag) + delta I);
+                           -1 (default): 1 for dense C, 0 for CSR */
     int32_t tiles_x;    /* grid-front partition: tiles along x (0 = auto) */
     int32_t tiles_y;    /* tiles along y (0 = auto) */
     int32_t batch;      /* b of the batch-zigzag traversal (default 20) */
@@ -97,6 +100,13 @@ typedef struct {
     double zdag_re;     /* first base-preconditioner site; NaN = region centre */
     double zdag_im;
     uint64_t seed;      /* seed of random start blocks */
+    double eta_abs;     /* absolute acceptance: a smallest Ritz value xi_1 <=
+                           eta_abs ||M(z)|| is accepted, because sigma_min lies
+                           in [0, xi_1] (Ritz values bound it from above)
+                           (default 1e-10; 0 disables) */
+    int32_t profile;    /* 1: time the operator-apply and matrix-core GEMM
+                           kernels with HIP events (fills the k_* stats) */
+    int32_t verbose;    /* 1: progress lines on stderr */
 } ps_params;
 
 typedef struct {
@@ -114,6 +124,15 @@ typedef struct {
     int64_t rounds;        /* scheduler rounds */
     double t_total_ms;     /* wall time of ps_eval */
     double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
+    /* with profile = 1: event-timed kernel classes (launches, device ms,
+     * algorithmic flops and bytes).  Class 0: operator applies C X, C^* Y
+     * (dense: matrix-core GEMM + split-K reduction; CSR: SpMM); class 1:
+     * preconditioner GEMMs (construction and K^{-1} W); class 2: Ritz
+     * extraction (per-point Jacobi SVD + residual). */
+    int64_t k_launches[4];
+    double k_ms[4];
+    double k_flops[4];
+    double k_bytes[4];
 } ps_stats;
 
 /* Per-point flag bits written to `flags`. */

@@ -18,6 +18,12 @@ extern "C" {
 ps_status ps_debug_apply(ps_matrix* h, int32_t herm, double z_re, double z_im, const double* X, int32_t w,
                          double* Y);
 
+/* Build the dense base preconditioner F (F^* F = N(z) + delta I, eq.
+ * (twolevel) with K = F^* F) at z in tile slot 0 and copy F^{-1} (n x n,
+ * column-major, host) out; gamma receives the ||F^{-1}||_2 estimate.
+ * Errors: PS_EUNSUPPORTED if the handle has no dense preconditioner. */
+ps_status ps_debug_precond(ps_matrix* h, double z_re, double z_im, double* Finv, double* gamma);
+
 /* The ||C||_2 estimate used in the acceptance tests (power iteration). */
 double ps_debug_norm(const ps_matrix* h);
 

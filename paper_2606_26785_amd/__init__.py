@@ -44,7 +44,8 @@ class ps_params(ctypes.Structure):
                 ("recycle", ctypes.c_int32), ("eta", ctypes.c_double), ("eta_svd", ctypes.c_double),
                 ("eta_proj", ctypes.c_double), ("omega", ctypes.c_double), ("tau_min", ctypes.c_double),
                 ("tau_max", ctypes.c_double), ("zdag_re", ctypes.c_double), ("zdag_im", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("eta_abs", ctypes.c_double), ("profile", ctypes.c_int32),
+                ("verbose", ctypes.c_int32)]
 
 
 class ps_stats(ctypes.Structure):
@@ -52,10 +53,16 @@ class ps_stats(ctypes.Structure):
         "points", "accepted", "refined", "uncertified", "lobpcg_iters", "proj_accepted",
         "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds")] + \
         [(n, ctypes.c_double) for n in ("t_total_ms", "t_ritz_ms", "t_lobpcg_ms", "t_update_ms",
-                                        "t_precond_ms")]
+                                        "t_precond_ms")] + \
+        [("k_launches", ctypes.c_int64 * 4), ("k_ms", ctypes.c_double * 4), ("k_flops", ctypes.c_double * 4),
+         ("k_bytes", ctypes.c_double * 4)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name.startswith("k_") else v
+        return out
 
 
 _lib = None
@@ -89,6 +96,8 @@ def load():
     lib.ps_last_error.restype = ctypes.c_char_p
     lib.ps_debug_apply.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int32, P]
     lib.ps_debug_apply.restype = ctypes.c_int
+    lib.ps_debug_precond.argtypes = [P, ctypes.c_double, ctypes.c_double, P, P]
+    lib.ps_debug_precond.restype = ctypes.c_int
     lib.ps_debug_norm.argtypes = [P]
     lib.ps_debug_norm.restype = ctypes.c_double
     _lib = lib
@@ -251,3 +260,13 @@ def create_from_workload(wl, params: ps_params | None = None, stream=None) -> Ma
     if wl.kind == "dense":
         return ps_create(dense=wl.dense, params=params, stream=stream)
     return ps_create(csr=(wl.rowptr, wl.colind, wl.vals), m=wl.m, n=wl.n, params=params, stream=stream)
+
+
+def debug_precond(mat: Matrix, z: complex):
+    """(F^{-1}, gamma) of the dense base preconditioner built at z (test hook)."""
+    m, n = mat.shape
+    F = np.empty((n, n), dtype=np.complex128, order="F")
+    g = np.zeros(1)
+    _check(load().ps_debug_precond(mat.handle, float(np.real(z)), float(np.imag(z)), _ptr(F), _ptr(g)),
+           "ps_debug_precond")
+    return F, float(g[0])

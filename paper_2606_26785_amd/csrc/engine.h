@@ -90,6 +90,19 @@ struct Tile {
     bool done() const { return cursor >= order.size(); }
 };
 
+// HIP-event timing of kernel classes (enabled by ps_params.profile)
+struct KProf {
+    std::vector<hipEvent_t> ev;   // pairs (start, stop)
+    std::vector<int> cls;
+    std::vector<double> flops, bytes;
+    size_t used = 0;
+    bool on = false;
+    int begin(hipStream_t s, int c, double fl, double by);
+    void end(hipStream_t s, int idx);
+    void collect(ps_stats& st);
+    ~KProf();
+};
+
 struct Engine {
     hipStream_t st = nullptr;
     ps_params P{};
@@ -135,6 +148,20 @@ struct Engine {
     HBuf<int> h_list;
     HBuf<zd> h_z;
 
+    // dense base preconditioner (per tile): K = F^* F, F the upper Cholesky
+    // factor of N(z_dag) + delta I; F^{-1} and F^{-*} kept explicitly
+    DBuf<zd> CtC, PN, Finv, FinvH, Dinv, T1p, pvec, d_zdag, zgemm_ws;
+    std::vector<zd> zdag;
+    std::vector<double> gam;
+    std::vector<char> has_prec;
+    bool use_prec = false;
+    void build_precond(const std::vector<int>& L);
+    void precond_apply(const int* dl, int nt, const zd* W, int64_t ws, zd* Y, int64_t ys);
+    void zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, const zd* A, int64_t lda, int64_t sA,
+               int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
+               double beta, int upper = 0, int tri = 0);
+
+    KProf prof;
     ps_stats stats{};
     std::vector<Tile> tiles;
     std::vector<zd> zs;       // grid points of the current eval

@@ -79,6 +79,47 @@ __global__ void k_scale_cols_rsqrt(const int* list, zd* A, int64_t stride, int64
 }
 
 // ---------------------------------------------------------------------------
+int KProf::begin(hipStream_t s, int c, double fl, double by)
+{
+    if (!on) return -1;
+    if (2 * used + 2 > ev.size()) {
+        size_t old = ev.size();
+        ev.resize(std::max<size_t>(64, 2 * old));
+        for (size_t i = old; i < ev.size(); ++i) HIPCHK(hipEventCreate(&ev[i]));
+    }
+    if (cls.size() <= used) { cls.resize(used + 1); flops.resize(used + 1); bytes.resize(used + 1); }
+    cls[used] = c;
+    flops[used] = fl;
+    bytes[used] = by;
+    HIPCHK(hipEventRecord(ev[2 * used], s));
+    return (int)used++;
+}
+void KProf::end(hipStream_t s, int idx)
+{
+    if (idx < 0) return;
+    HIPCHK(hipEventRecord(ev[2 * idx + 1], s));
+}
+void KProf::collect(ps_stats& st)
+{
+    for (int c = 0; c < 4; ++c) { st.k_launches[c] = 0; st.k_ms[c] = 0; st.k_flops[c] = 0; st.k_bytes[c] = 0; }
+    for (size_t i = 0; i < used; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventSynchronize(ev[2 * i + 1]));
+        HIPCHK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+        int c = cls[i];
+        st.k_launches[c] += 1;
+        st.k_ms[c] += ms;
+        st.k_flops[c] += flops[i];
+        st.k_bytes[c] += bytes[i];
+    }
+    used = 0;
+}
+KProf::~KProf()
+{
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------------------
 void Engine::upload_list(const std::vector<int>& L, DBuf<int>& dst)
 {
     h_list.alloc(L.size() + 1);
@@ -227,7 +268,7 @@ void Engine::orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, 
         sa.list = dlist;
         sa.r = cols;
         sa.max_sweeps = 40;
-        sa.drop = 1e-10;
+        sa.drop = 1e-6;   // directions this small lose orthogonality ~ eps / 1e-6: refill them
         sa.R = Rsm.p;
         sa.strideR = (int64_t)9 * r * r;
         sa.ldR = 3 * r;
@@ -240,14 +281,15 @@ void Engine::orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, 
                 m, rows, 1.0, 0.0);
         launch_copy_cols(dlist, nt, Tn1.p, (int64_t)m * 3 * r, m, W, wstride, ldw, rows, cols, st);
         launch_randfill(dlist, nt, W, wstride, ldw, rows, cols, mask.p, seed + 7919ull * pass, st);
-        // check whether any direction was refilled
+        if (pass == 0) continue;
+        // check whether any direction was refilled in this pass
         h_small.alloc(T + 1);
         HIPCHK(hipMemcpyAsync(h_small.p, mask.p, sizeof(uint32_t) * T, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const uint32_t* hm = (const uint32_t*)h_small.p;
         bool any = false;
         for (int t : L) any |= (hm[t] != 0);
-        if (!any && pass >= 1) break;
+        if (!any) break;
     }
 }
 
@@ -277,7 +319,9 @@ void Engine::apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xst
         a.part = apply_ws.p;
         int64_t N = (int64_t)nt * w;
         a.splitk = (int)std::max<int64_t>(1, (int64_t)(apply_ws.n / ((size_t)a.m * N)));
+        int pi = prof.begin(st, 0, 8.0 * a.m * a.K * N, 16.0 * ((double)a.m * a.K + (double)a.K * N + (double)a.m * N));
         launch_dense_apply(a, st);
+        prof.end(st, pi);
     } else {
         CsrApplyArgs a;
         memset(&a, 0, sizeof(a));
@@ -295,7 +339,12 @@ void Engine::apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xst
         a.z = dz;
         a.conjz = herm ? 1 : 0;
         a.nshift = op.n;
+        int64_t N = (int64_t)nt * w;
+        double rows_in = herm ? (double)op.m : (double)op.n;
+        int pi = prof.begin(st, 0, 8.0 * op.nnz * N,
+                            20.0 * op.nnz + 8.0 * a.m + 16.0 * N * (rows_in + (double)a.m));
         launch_csr_apply(a, st);
+        prof.end(st, pi);
     }
 }
 
@@ -371,8 +420,18 @@ void Engine::create(const ps_matrix_desc* d, const ps_params* p, hipStream_t s)
     m = op.m;
     r = P.r;
     K = P.k_max;
+    if (P.precond < 0) P.precond = (op.kind == PS_DENSE) ? 1 : 0;
+    if (P.precond > 0 && op.kind != PS_DENSE)
+        throw InvalidArg("precond = 1 needs a dense matrix in this build");
+    use_prec = P.precond > 0;
     size_for(1);
     estimate_norm();
+    if (use_prec) {
+        // C^* C once, for N(z) = C^*C - conj(z) S^*C - z C^*S + |z|^2 I
+        CtC.alloc((size_t)n * n);
+        zgemm(nullptr, 1, n, n, m, op.A.p, m, 0, 1, op.A.p, m, 0, CtC.p, n, 0, 1.0, 0.0);
+        HIPCHK(hipStreamSynchronize(st));
+    }
 }
 
 // ||C||_2 by power iteration on C^* C (60 steps, on the device), scaled by 1.01.
@@ -422,7 +481,7 @@ void Engine::size_for(int tiles)
     Csm.alloc(t * K * 3 * r); Tsm.alloc(t * 9 * r * r);
     Qt.alloc(t * K * K); Upp.alloc(t * r * r); Ucoef.alloc(t * K * r); X0c.alloc(t * K * r);
     xi.alloc(t * 3 * r); nrm2.alloc(t * 3 * r); xi_out.alloc(t * 3 * r);
-    mask.alloc(t); cdim.alloc(t); d_list.alloc(t); d_list2.alloc(t); d_jobsrc.alloc(t);
+    mask.alloc(t); cdim.alloc(3 * t); d_list.alloc(t); d_list2.alloc(t); d_jobsrc.alloc(t);
     d_z.alloc(t);
     const size_t J = t * B;
     j_tile.alloc(J); j_z.alloc(J); j_G.alloc(J * K * r);
@@ -432,6 +491,20 @@ void Engine::size_for(int tiles)
     const size_t maxw = (size_t)std::max(r, P.rbar);
     apply_ws.alloc((size_t)std::max(m, n) * std::max<size_t>(t * maxw, 64) * 4);
     norm_ws.alloc(std::max<size_t>(1 << 20, t * 3 * r * 256));
+    {
+        std::vector<int> cv(3 * t);
+        for (size_t i = 0; i < t; ++i) { cv[i] = r; cv[t + i] = 2 * r; cv[2 * t + i] = 3 * r; }
+        HIPCHK(hipMemcpy(cdim.p, cv.data(), sizeof(int) * 3 * t, hipMemcpyHostToDevice));
+    }
+    if (use_prec) {
+        const size_t nn = (size_t)n * n;
+        PN.alloc(t * nn); Finv.alloc(t * nn); FinvH.alloc(t * nn);
+        Dinv.alloc(t * n * PRE_NB); T1p.alloc(t * n * PRE_NB); pvec.alloc(t * 2 * n); d_zdag.alloc(t);
+        zgemm_ws.alloc(std::max<size_t>((size_t)32 << 20, t * (size_t)n * r * 16));
+    }
+    zdag.assign(t, zmake(0.0, 0.0));
+    gam.assign(t, 0.0);
+    has_prec.assign(t, 0);
     h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r)); h_nrm2.alloc(t * 3 * r);
     h_small.alloc(t * 4 + 8); h_C.alloc(t * K * r + 8); h_list.alloc(t + 1); h_z.alloc(t + J);
 }
@@ -462,19 +535,10 @@ void Engine::lobpcg(const std::vector<int>& Lin, std::vector<double>& sigma, std
     BlockList Lcx = bl_empty(m);
     bl_add(Lcx, CS.p, sC, m, r, nullptr, 0);
     r_factor(d_list.p, (int)L.size(), Lcx, r, nullptr, 0, r, Rsm.p, (int64_t)9 * r * r, r3);
-    std::vector<int> cd(T, r);
-    auto set_cdim = [&](int c) {
-        std::vector<int> v(T, c);
-        h_small.alloc(T + 8);
-        int* hp = (int*)h_small.p;
-        for (int i = 0; i < T; ++i) hp[i] = c;
-        HIPCHK(hipMemcpyAsync(cdim.p, hp, sizeof(int) * T, hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
-    };
-    set_cdim(r);
+    auto set_cdim = [&](int c) { return cdim.p + (size_t)T * (c / r - 1); };
     RRArgs ra;
     memset(&ra, 0, sizeof(ra));
-    ra.cdim = cdim.p;
+    ra.cdim = set_cdim(r);
     ra.r = r;
     ra.max_sweeps = 40;
     ra.R = Rsm.p;
@@ -512,11 +576,16 @@ void Engine::lobpcg(const std::vector<int>& Lin, std::vector<double>& sigma, std
         for (int t = 0; t < T; ++t) hz_abs[t] = sqrt(zabs2(h_z[t]));
     }
     const int maxit = P.max_iters;
+    // floor of eq. (tolSVD): the residual C(z)^*(C(z) x) - xi^2 x is itself
+    // computed with an error of order sqrt(n) eps ||C(z)||^2, so a floor of
+    // exactly eps ||C(z)||^2 can be out of reach; the constant scales with it
+    const double floor_c = std::max(16.0, 4.0 * sqrt((double)n));
     for (int it = 1; it <= maxit && !L.empty(); ++it) {
         const int nt = (int)L.size();
         stats.lobpcg_iters += nt;
-        // W <- K^{-1} W (K = I), into S[:, r:2r]
-        launch_copy_cols(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r, st);
+        // W <- K^{-1} W, into S[:, r:2r]
+        if (use_prec) precond_apply(d_list.p, nt, Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
+        else launch_copy_cols(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r, st);
         BlockList Lxp = bl_empty(n);
         bl_add(Lxp, S.p, sS, n, r, nullptr, 0);
         if (hasP) bl_add(Lxp, S.p + (size_t)2 * n * r, sS, n, r, nullptr, 0);
@@ -527,7 +596,7 @@ void Engine::lobpcg(const std::vector<int>& Lin, std::vector<double>& sigma, std
         BlockList Lcs = bl_empty(m);
         bl_add(Lcs, CS.p, sC, m, c, nullptr, 0);
         r_factor(d_list.p, nt, Lcs, c, nullptr, 0, c, Rsm.p, (int64_t)9 * r * r, r3);
-        set_cdim(c);
+        ra.cdim = set_cdim(c);
         ra.list = d_list.p;
         launch_rr_hl(ra, nt, c, st);
         BlockList Ls = bl_empty(n);
@@ -554,7 +623,7 @@ void Engine::lobpcg(const std::vector<int>& Lin, std::vector<double>& sigma, std
             double nz = nC + hz_abs[t];
             double x0 = h_xi[(size_t)t * r3];
             double w0 = sqrt(std::max(0.0, h_nrm2[(size_t)t * r3]));
-            return w0 <= std::max(P.eta_svd * nz * x0, nz * nz * EPSM);
+            return w0 <= std::max(P.eta_svd * nz * x0, floor_c * nz * nz * EPSM) || x0 <= P.eta_abs * nz;
         };
         std::vector<int> cand;
         for (int t : L) if (passes(t)) cand.push_back(t);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 void Engine::upload_k()
@@ -192,6 +193,8 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
 {
     auto t_start = std::chrono::steady_clock::now();
     memset(&stats, 0, sizeof(stats));
+    prof.on = P.profile != 0;
+    prof.used = 0;
     const int nx = g->nx, ny = g->ny;
     const int64_t npts = (int64_t)nx * ny;
     zs.resize(npts);
@@ -210,6 +213,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     tile_orders(nx, ny, tx, ty, b, tiles);
     size_for((int)tiles.size());
     for (auto& t : tiles) { t.cursor = 0; t.k = 0; }
+    std::fill(has_prec.begin(), has_prec.end(), 0);
     upload_k();
     std::vector<uint8_t> fl(npts, 0);
     std::vector<double> sig(npts, 0.0);
@@ -271,6 +275,8 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 ra.max_sweeps = 40;
                 ra.mode = 0;
                 ra.eta = P.eta;
+                ra.floor_c = std::max(16.0, 4.0 * sqrt((double)n));
+                ra.eta_abs = P.eta_abs;
                 ra.xi = j_xi.p;
                 ra.res = j_res.p;
                 ra.ldxi = 1;
@@ -278,7 +284,9 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 ra.strideG = (int64_t)K * r;
                 ra.ldG = K;
                 ra.accept = j_acc.p;
+                int pi = prof.begin(st, 2, 0.0, 0.0);
                 launch_ritz(ra, K, st);
+                prof.end(st, pi);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipMemcpyAsync(h_acc.p, j_acc.p, nj, hipMemcpyDeviceToHost, st));
                 HIPCHK(hipMemcpyAsync(h_xi.p, j_xi.p, sizeof(double) * nj, hipMemcpyDeviceToHost, st));
@@ -334,6 +342,36 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             round_seed = round_seed * 6364136223846793005ull + 1442695040888963407ull;
             launch_randfill(d_list.p, (int)Rr.size(), S.p, sS, n, n, r, nullptr, round_seed, st);
         }
+        // base preconditioner: build at the first refined point of a tile and
+        // rebuild at z when the Weyl bound of eq. (tauRecycle) on the largest
+        // pencil eigenvalue, (sqrt(lambda_n^dag) + gamma |z - z_dag|)^2 with
+        // lambda_n^dag <= 1 for F^* F = N(z_dag) + delta I, exceeds tau_max.
+        // Without the coarse (two-level) correction nothing lifts the small
+        // end of the pencil spectrum, which Weyl's inequality bounds below by
+        // (1 - gamma |z - z_dag|)^2; the same rule is then applied to the
+        // condition number bound ((1 + g)/(1 - g))^2 <= tau_max.
+        if (use_prec) {
+            std::vector<int> Rb;
+            for (int t : R) {
+                zd z = zs[tiles[t].order[tiles[t].cursor]];
+                bool rebuild = !has_prec[t];
+                if (!rebuild) {
+                    double g = gam[t] * sqrt(zabs2(zsub(z, zdag[t])));
+                    double bound = (1.0 + g) * (1.0 + g);
+                    if (g >= 1.0) rebuild = true;
+                    else rebuild = bound / ((1.0 - g) * (1.0 - g)) > P.tau_max;
+                }
+                if (rebuild) {
+                    zdag[t] = z;
+                    Rb.push_back(t);
+                    fl[tiles[t].order[tiles[t].cursor]] |= PS_FLAG_REBUILD;
+                }
+            }
+            auto tp0 = now();
+            build_precond(Rb);
+            HIPCHK(hipStreamSynchronize(st));
+            stats.t_precond_ms += ms(tp0, now());
+        }
         // current z of each refined tile
         h_z.alloc((size_t)T + 8);
         for (int t : R) h_z[t] = zs[tiles[t].order[tiles[t].cursor]];
@@ -355,7 +393,14 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         }
         if (P.recycle) update_store(R);
         t_upd += ms(t2, now());
+        if (P.verbose && stats.rounds % 20 == 0) {
+            fprintf(stderr, "[ps] round %lld: accepted %lld refined %lld rebuilds %lld iters %lld  %.1f s\n",
+                    (long long)stats.rounds, (long long)stats.accepted, (long long)stats.refined,
+                    (long long)stats.rebuilds, (long long)stats.lobpcg_iters, ms(t_start, now()) / 1000.0);
+            fflush(stderr);
+        }
     }
+    if (prof.on) prof.collect(stats);
     stats.points = npts;
     for (int64_t p = 0; p < npts; ++p) sigma[p] = sig[p];
     if (flags) memcpy(flags, fl.data(), npts);

@@ -163,3 +163,123 @@ void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s)
     dim3 g((unsigned)((a.m + NT - 1) / NT), a.ntiles);
     hipLaunchKernelGGL(k_csr_apply, g, dim3(NT), 0, s, a);
 }
+
+// ---------------------------------------------------------------------------
+// Batched complex GEMM on the FP64 matrix cores:
+//   C_b[0:M, 0:N] = alpha op(A_b) B_b + beta C_b,  op(A) = A or A^*,
+// one matrix triple per entry of the batch list (pointer + list[i] * stride).
+// With upper != 0 only 64 x 32 tiles that touch the upper triangle of C are
+// computed (Hermitian rank-k updates).  The K loop of a workgroup finishes
+// before its epilogue writes, so C may alias B when M <= 64 (in-place
+// left-multiplication of a panel by a small matrix).
+__global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
+{
+    __shared__ zd As[BK][BM + 1];
+    __shared__ zd Bs[BK][BN + 1];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t i0 = (int64_t)blockIdx.x * BM;
+    const int64_t j0 = (int64_t)blockIdx.y * BN;
+    const int nb = gridDim.z / a.splitk;
+    const int bidx = blockIdx.z % nb, split = blockIdx.z / nb;
+    const int tile = a.list ? a.list[bidx] : bidx;
+    if (a.upper && i0 > j0 + BN - 1) return;
+    const int64_t kc = (a.K + a.splitk - 1) / a.splitk;
+    int64_t kbeg = (int64_t)split * kc;
+    int64_t kend = (kbeg + kc < a.K) ? kbeg + kc : a.K;
+    // triangular A: rows i0..i0+63 have nonzeros only in k >= i0 (upper) or
+    // k < i0 + 64 (lower); the staging masks below keep the rest at zero
+    if (a.tri == 1 && kbeg < i0) kbeg = (i0 / BK) * BK > kbeg ? (i0 / BK) * BK : kbeg;
+    if (a.tri == 2 && kend > i0 + BM) kend = i0 + BM;
+    const zd* A = a.A + (size_t)tile * a.strideA;
+    const zd* B = a.B + (size_t)tile * a.strideB;
+    zd* C = a.C + (size_t)tile * a.strideC;
+    dvec4 acc_re[2], acc_im[2];
+    for (int c = 0; c < 2; ++c) {
+        acc_re[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
+        acc_im[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
+    }
+    const int mrow = lane & 15, kq = lane >> 4;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        if (a.opA == 0) {
+            for (int e = tid; e < BM * BK; e += NT) {
+                int ii = e % BM, kk = e / BM;
+                int64_t gi = i0 + ii, gk = k0 + kk;
+                As[kk][ii] = (gi < a.M && gk < kend) ? A[gi + gk * a.lda] : zmake(0.0, 0.0);
+            }
+        } else {
+            for (int e = tid; e < BM * BK; e += NT) {
+                int kk = e % BK, ii = e / BK;
+                int64_t gi = i0 + ii, gk = k0 + kk;
+                As[kk][ii] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
+            }
+        }
+        for (int e = tid; e < BN * BK; e += NT) {
+            int kk = e % BK, jj = e / BK;
+            int64_t gj = j0 + jj, gk = k0 + kk;
+            Bs[kk][jj] = (gj < a.N && gk < kend) ? B[gk + gj * a.ldb] : zmake(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            zd av = As[ks + kq][wave * 16 + mrow];
+            double ar = av.x, ai = av.y, nai = -av.y;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                zd xv = Bs[ks + kq][cb * 16 + mrow];
+                acc_re[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xv.x, acc_re[cb], 0, 0, 0);
+                acc_re[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, xv.y, acc_re[cb], 0, 0, 0);
+                acc_im[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xv.y, acc_im[cb], 0, 0, 0);
+                acc_im[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xv.x, acc_im[cb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        int64_t col = j0 + cb * 16 + (lane & 15);
+        if (col >= a.N) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int64_t row = i0 + wave * 16 + (lane >> 4) + 4 * v;
+            if (row >= a.M) continue;
+            if (a.splitk > 1) {
+                a.ws[((size_t)split * nb + bidx) * a.M * a.N + row + (size_t)col * a.M] =
+                    zmake(acc_re[cb][v], acc_im[cb][v]);
+                continue;
+            }
+            zd val = zmake(a.alpha * acc_re[cb][v], a.alpha * acc_im[cb][v]);
+            zd* cp = C + row + col * a.ldc;
+            if (a.beta != 0.0) val = zadd(val, *cp);
+            *cp = val;
+        }
+    }
+}
+
+// sum of the split-K partials into C (alpha, beta as in k_zgemm)
+__global__ void __launch_bounds__(NT) k_zgemm_reduce(ZgemmArgs a, int nb)
+{
+    const int bidx = blockIdx.y;
+    const int tile = a.list ? a.list[bidx] : bidx;
+    int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= a.M * a.N) return;
+    int64_t row = e % a.M, col = e / a.M;
+    zd s = zmake(0.0, 0.0);
+    for (int sp = 0; sp < a.splitk; ++sp) s = zadd(s, a.ws[((size_t)sp * nb + bidx) * a.M * a.N + e]);
+    zd* cp = a.C + (size_t)tile * a.strideC + row + col * a.ldc;
+    zd val = zscale(s, a.alpha);
+    if (a.beta != 0.0) val = zadd(val, *cp);
+    *cp = val;
+}
+
+void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s)
+{
+    if (nbatch <= 0 || a.M <= 0 || a.N <= 0) return;
+    const int sk = a.splitk > 1 ? a.splitk : 1;
+    dim3 g((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + BN - 1) / BN), nbatch * sk);
+    hipLaunchKernelGGL(k_zgemm, g, dim3(NT), 0, s, a);
+    if (sk > 1) {
+        dim3 g2((unsigned)((a.M * a.N + NT - 1) / NT), nbatch);
+        hipLaunchKernelGGL(k_zgemm_reduce, g2, dim3(NT), 0, s, a, nbatch);
+    }
+}

@@ -1,0 +1,143 @@
+// Dense base preconditioner K = F^* F ~ N(z_dag) = (C - z_dag S)^* (C - z_dag S)
+// (Sec. 3, eq. (twolevel) and the reconstruction rule of Sec. 3.3): F is the
+// upper Cholesky factor of N(z_dag) + delta I, computed by a right-looking
+// blocked Cholesky whose trailing updates run on the matrix cores (k_zgemm),
+// and F^{-1} is formed block column by block column alongside it, so that
+// K^{-1} W = F^{-1} (F^{-*} W) is two matrix-core products.
+#include "zdev.h"
+#include "kernels.h"
+
+#define NT 256
+
+// N = C^*C - conj(z) S^*C - z C^*S + (|z|^2 + delta) I for each tile in list
+__global__ void k_form_normal(const int* list, const zd* CtC, const zd* C, int64_t ldc, const zd* CH, int64_t n,
+                              const zd* zdag, double delta, zd* N, int64_t strideN)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= n * n) return;
+    int64_t i = e % n, j = e / n;
+    zd z = zdag[tile];
+    zd v = CtC[i + j * n];
+    zd c = C[i + j * ldc];      // S^* C: first n rows of C
+    zd ch = CH[i + j * n];      // C^* S: first n columns of C^*
+    v = zsub(v, zmul(zconj(z), c));
+    v = zsub(v, zmul(z, ch));
+    if (i == j) v.x += zabs2(z) + delta;
+    N[(size_t)tile * strideN + i + j * n] = v;
+}
+
+void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int64_t ldc, const zd* CH,
+                        int64_t n, const zd* zdag, double delta, zd* N, int64_t strideN, hipStream_t s)
+{
+    if (nt <= 0) return;
+    dim3 g((unsigned)((n * n + NT - 1) / NT), nt);
+    hipLaunchKernelGGL(k_form_normal, g, dim3(NT), 0, s, list, CtC, C, ldc, CH, n, zdag, delta, N, strideN);
+}
+
+// Diagonal block (kb <= 32) of the blocked Cholesky: R_kk with R_kk^* R_kk = A_kk
+// (upper triangle of A_kk read), written back into A; its inverse written to
+// Dinv (rows k0.., ld n) and to the diagonal block of Finv (zeros below the
+// diagonal).  Pivots are floored at `floor_piv` (the matrix is N + delta I,
+// positive definite in exact arithmetic).
+__global__ void __launch_bounds__(NT) k_chol_diag(const int* list, zd* A, int64_t strideA, int64_t n, int64_t k0,
+                                                  int kb, zd* Dinv, int64_t strideD, zd* Finv, int64_t strideF,
+                                                  double floor_piv)
+{
+    __shared__ zd R[32][33];
+    __shared__ zd X[32][33];
+    __shared__ double piv;
+    const int tile = list[blockIdx.x];
+    const int tid = threadIdx.x;
+    zd* Ab = A + (size_t)tile * strideA + k0 + k0 * n;
+    for (int e = tid; e < kb * kb; e += NT) {
+        int i = e % kb, j = e / kb;
+        R[i][j] = (i <= j) ? Ab[i + (int64_t)j * n] : zmake(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+        if (tid == 0) {
+            double d = R[j][j].x;
+            if (!(d > floor_piv)) d = floor_piv;
+            piv = sqrt(d);
+        }
+        __syncthreads();
+        const double p = piv;
+        // row j of R: R[j][c] = A[j][c] / p for c >= j
+        for (int c = j + tid; c < kb; c += NT) R[j][c] = (c == j) ? zmake(p, 0.0) : zscale(R[j][c], 1.0 / p);
+        __syncthreads();
+        // trailing: A[a][c] -= conj(R[j][a]) R[j][c], j < a <= c
+        for (int e = tid; e < kb * kb; e += NT) {
+            int a2 = e % kb, c = e / kb;
+            if (a2 > j && c >= a2) R[a2][c] = zsub(R[a2][c], zcmul(R[j][a2], R[j][c]));
+        }
+        __syncthreads();
+    }
+    // X = R^{-1} (upper): column c by back substitution, one thread per column
+    for (int c = tid; c < kb; c += NT) {
+        for (int i = kb - 1; i >= 0; --i) {
+            if (i > c) { X[i][c] = zmake(0.0, 0.0); continue; }
+            zd s = zmake(i == c ? 1.0 : 0.0, 0.0);
+            for (int l = i + 1; l <= c; ++l) s = zsub(s, zmul(R[i][l], X[l][c]));
+            double rii = R[i][i].x;
+            X[i][c] = zscale(s, 1.0 / rii);
+        }
+    }
+    __syncthreads();
+    zd* Db = Dinv + (size_t)tile * strideD + k0;
+    zd* Fb = Finv + (size_t)tile * strideF + k0 + k0 * n;
+    for (int e = tid; e < kb * kb; e += NT) {
+        int i = e % kb, j = e / kb;
+        Ab[i + (int64_t)j * n] = (i <= j) ? R[i][j] : zmake(0.0, 0.0);
+        Db[i + (int64_t)j * n] = X[i][j];
+        Fb[i + (int64_t)j * n] = X[i][j];
+    }
+}
+
+void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
+                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, hipStream_t s)
+{
+    if (nt <= 0) return;
+    hipLaunchKernelGGL(k_chol_diag, dim3(nt), dim3(NT), 0, s, list, A, strideA, n, k0, kb, Dinv, strideD, Finv,
+                       strideF, floor_piv);
+}
+
+// batched conjugate transpose of square n x n matrices (per tile)
+__global__ void k_conj_transpose_b(const int* list, const zd* A, int64_t stride, int64_t n, zd* B)
+{
+    __shared__ zd t[32][33];
+    const int tile = list[blockIdx.z];
+    const zd* Ab = A + (size_t)tile * stride;
+    zd* Bb = B + (size_t)tile * stride;
+    int64_t bi = (int64_t)blockIdx.x * 32, bj = (int64_t)blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        int64_t i = bi + threadIdx.x, j = bj + k;
+        if (i < n && j < n) t[k][threadIdx.x] = Ab[i + j * n];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        int64_t j = bj + threadIdx.x, i = bi + k;
+        if (i < n && j < n) Bb[j + i * n] = zconj(t[threadIdx.x][k]);
+    }
+}
+
+void launch_conj_transpose_b(const int* list, int nt, const zd* A, int64_t stride, int64_t n, zd* B, hipStream_t s)
+{
+    if (nt <= 0) return;
+    dim3 g((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32), nt);
+    hipLaunchKernelGGL(k_conj_transpose_b, g, dim3(32, 8), 0, s, list, A, stride, n, B);
+}
+
+__global__ void k_zero_tiles(const int* list, zd* A, int64_t stride, int64_t count)
+{
+    const int tile = list[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e < count) A[(size_t)tile * stride + e] = zmake(0.0, 0.0);
+}
+
+void launch_zero_tiles(const int* list, int nt, zd* A, int64_t stride, int64_t count, hipStream_t s)
+{
+    if (nt <= 0 || count <= 0) return;
+    dim3 g((unsigned)((count + NT - 1) / NT), nt);
+    hipLaunchKernelGGL(k_zero_tiles, g, dim3(NT), 0, s, list, A, stride, count);
+}

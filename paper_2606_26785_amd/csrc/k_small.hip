@@ -318,8 +318,8 @@ __global__ void __launch_bounds__(NT) k_ritz(RitzArgs a)
         int acc = 1;
         if (a.mode == 0) {
             double xi0 = sv[perm[0]];
-            double thr = fmax(a.eta * xi0 * nrm, nrm * nrm * 2.220446049250313e-16);
-            acc = (sres[0] <= thr);
+            double thr = fmax(a.eta * xi0 * nrm, a.floor_c * nrm * nrm * 2.220446049250313e-16);
+            acc = (sres[0] <= thr) || (xi0 <= a.eta_abs * nrm);
         } else {
             for (int v = 0; v < nv; ++v) acc &= (sres[v] <= a.eta * nrm);
         }

@@ -270,7 +270,7 @@ __global__ void k_scale_cols(const int* list, zd* A, int64_t stride, int64_t lda
     if (e >= rows * cols) return;
     int64_t i = e % rows, j = e / rows;
     double v = d[(size_t)tile * ldd + j];
-    double f = invert ? (v > 0.0 ? 1.0 / v : 0.0) : v;
+    double f = (invert == 2) ? (v > 0.0 ? 1.0 / sqrt(v) : 0.0) : invert ? (v > 0.0 ? 1.0 / v : 0.0) : v;
     zd* p = A + (size_t)tile * stride + i + j * lda;
     *p = zscale(*p, f);
 }

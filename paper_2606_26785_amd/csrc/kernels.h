@@ -15,6 +15,8 @@ struct RitzArgs {
     const zd* Rres; int64_t strideRres; int ldRres; int nres;
     int nv, ng, max_sweeps, mode;
     double eta;
+    double floor_c;        // floor of tolC: floor_c * eps * nrm^2
+    double eta_abs;        // accept when xi_0 <= eta_abs * nrm (upper-bound certificate)
     double* xi; double* res; int ldxi;     // per job nv values
     zd* Gout; int64_t strideG; int ldG;    // per job k x ng right vectors
     uint8_t* accept;
@@ -164,3 +166,27 @@ struct CsrApplyArgs {
     const zd* z; int conjz; int64_t nshift;
 };
 void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s);
+
+// batched complex GEMM C = alpha op(A) B + beta C on the matrix cores
+struct ZgemmArgs {
+    const int* list;                 // batch -> tile (NULL: identity)
+    int64_t M, N, K;
+    const zd* A; int64_t lda, strideA; int opA;   // opA: 0 = A, 1 = A^*
+    const zd* B; int64_t ldb, strideB;
+    zd* C; int64_t ldc, strideC;
+    double alpha, beta;
+    int upper;                       // compute only tiles touching the upper triangle
+    int tri;                         // 1: A upper triangular, 2: A lower triangular (skip zero blocks)
+    int splitk;                      // > 1: K split over workgroups, partials in ws
+    zd* ws;                          // splitk * nbatch * M * N partial products
+};
+void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s);
+
+// dense base preconditioner (k_precond.hip)
+#define PRE_NB 32
+void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int64_t ldc, const zd* CH,
+                        int64_t n, const zd* zdag, double delta, zd* N, int64_t strideN, hipStream_t s);
+void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
+                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, hipStream_t s);
+void launch_conj_transpose_b(const int* list, int nt, const zd* A, int64_t stride, int64_t n, zd* B, hipStream_t s);
+void launch_zero_tiles(const int* list, int nt, zd* A, int64_t stride, int64_t count, hipStream_t s);

@@ -29,7 +29,7 @@ void ps_default_params(ps_params* p)
     p->rbar = 16;
     p->kbar_max = 64;
     p->max_iters = 300;
-    p->precond = 0;
+    p->precond = -1;
     p->tiles_x = 0;
     p->tiles_y = 0;
     p->batch = 20;
@@ -43,6 +43,7 @@ void ps_default_params(ps_params* p)
     p->zdag_re = NAN;
     p->zdag_im = NAN;
     p->seed = 20261203ull;
+    p->eta_abs = 1e-10;
 }
 
 const char* ps_strerror(ps_status s)
@@ -82,8 +83,11 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
     if (p.kbar_max < p.rbar || p.kbar_max % p.rbar || p.kbar_max > 64)
         return fail(PS_EINVAL, "kbar_max must be a multiple of rbar, <= 64");
     if (p.max_iters < 1 || p.batch < 1) return fail(PS_EINVAL, "max_iters and batch must be positive");
-    if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0)) return fail(PS_EINVAL, "bad tolerances");
-    if (p.precond != 0) return fail(PS_EUNSUPPORTED, "precond != 0 is not available in this build");
+    if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0) || !(p.eta_abs >= 0) || p.eta_abs > 1e-8)
+        return fail(PS_EINVAL, "bad tolerances");
+    if (p.precond > 1 || p.precond < -1) return fail(PS_EINVAL, "precond must be -1, 0 or 1");
+    if (p.precond == 1 && d->kind != PS_DENSE)
+        return fail(PS_EUNSUPPORTED, "the base preconditioner needs a dense matrix in this build");
     if (d->kind == PS_DENSE && !d->on_device) {
         for (int64_t j = 0; j < d->n; ++j)
             for (int64_t i = 0; i < 2 * d->m; ++i)
@@ -189,3 +193,24 @@ extern "C" ps_status ps_debug_apply(ps_matrix* h, int32_t herm, double z_re, dou
 }
 
 extern "C" double ps_debug_norm(const ps_matrix* h) { return h ? h->eng.op.normC : 0.0; }
+
+// Build the dense base preconditioner of slot 0 at z and copy F^{-1} (n x n,
+// column-major) to the host; returns gamma = ||F^{-1}||_2 estimate.
+extern "C" ps_status ps_debug_precond(ps_matrix* h, double z_re, double z_im, double* Finv_out, double* gamma_out)
+{
+    if (!h || !Finv_out) return fail(PS_EINVAL, "NULL argument");
+    try {
+        Engine& E = h->eng;
+        if (!E.use_prec) return fail(PS_EUNSUPPORTED, "no dense preconditioner on this handle");
+        if (E.T < 1 || E.zdag.empty()) E.size_for(std::max(E.T, 1));
+        E.zdag[0] = zmake(z_re, z_im);
+        std::vector<int> L = {0};
+        E.build_precond(L);
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(Finv_out, E.Finv.p, sizeof(zd) * E.n * E.n, hipMemcpyDeviceToHost));
+        if (gamma_out) *gamma_out = E.gam[0];
+        return PS_OK;
+    } catch (const std::exception& e) {
+        return fail(PS_EDEVICE, e.what());
+    }
+}
