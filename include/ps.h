@@ -101,9 +101,12 @@ typedef struct {
     double zdag_im;
     uint64_t seed;      /* seed of random start blocks */
     double eta_abs;     /* absolute acceptance: a smallest Ritz value xi_1 <=
-                           eta_abs ||M(z)|| is accepted, because sigma_min lies
+                           eta_abs ||C||_2 is accepted, because sigma_min lies
                            in [0, xi_1] (Ritz values bound it from above)
-                           (default 1e-10; 0 disables) */
+                           (default 1e-9; 0 disables; at most 1e-8) */
+    double rho_small;   /* refined points whose recycled Ritz value is below
+                           rho_small ||M(z)|| run LOBPCG with K = I and build no
+                           base preconditioner (default 1e-5) */
     int32_t profile;    /* 1: time the operator-apply and matrix-core GEMM
                            kernels with HIP events (fills the k_* stats) */
     int32_t verbose;    /* 1: progress lines on stderr */

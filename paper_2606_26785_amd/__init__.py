@@ -44,7 +44,8 @@ class ps_params(ctypes.Structure):
                 ("recycle", ctypes.c_int32), ("eta", ctypes.c_double), ("eta_svd", ctypes.c_double),
                 ("eta_proj", ctypes.c_double), ("omega", ctypes.c_double), ("tau_min", ctypes.c_double),
                 ("tau_max", ctypes.c_double), ("zdag_re", ctypes.c_double), ("zdag_im", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("eta_abs", ctypes.c_double), ("profile", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("eta_abs", ctypes.c_double), ("rho_small", ctypes.c_double),
+                ("profile", ctypes.c_int32),
                 ("verbose", ctypes.c_int32)]
 
 

@@ -154,6 +154,8 @@ struct Engine {
     std::vector<zd> zdag;
     std::vector<double> gam;
     std::vector<char> has_prec;
+    std::vector<char> usek;          // per tile: this refinement uses the base preconditioner
+    DBuf<int> d_listK, d_listI;
     bool use_prec = false;
     void build_precond(const std::vector<int>& L);
     void precond_apply(const int* dl, int nt, const zd* W, int64_t ws, zd* Y, int64_t ys);
@@ -190,8 +192,16 @@ struct Engine {
                   zd* R, int64_t strideR, int ldR);
 
     // ---- algorithm steps
-    void lobpcg(const std::vector<int>& L, std::vector<double>& sigma, std::vector<int>& iters,
-                std::vector<int>& ok, uint64_t seed);
+    // LOBPCG-SVD as a per-tile state machine: lob_start runs the first
+    // Rayleigh-Ritz-SVD on the start block of the listed tiles, lob_step one
+    // iteration for every listed tile (tiles may be at different iterations).
+    std::vector<int> lob_it;          // per tile: iteration count (0 = after start)
+    std::vector<double> lob_sigma;    // per tile: smallest Ritz value at exit
+    std::vector<zd> h_zt;             // per tile: current grid point
+    DBuf<int> d_cdimt, d_pcols;       // per tile: width of S, width of P
+    void lob_start(const std::vector<int>& L, uint64_t seed);
+    // returns the tiles that finished (converged, or at max_iters: ok = 0)
+    void lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>& done, std::vector<int>& ok);
     void update_store(const std::vector<int>& L);
     void upload_k();
     void refresh_store(const std::vector<int>& L);

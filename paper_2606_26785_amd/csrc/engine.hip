@@ -152,7 +152,8 @@ void Engine::gram(const int* dlist, int nt, const BlockList& A, const BlockList&
     // rows per chunk: enough chunks to fill the GPU, within the workspace
     int64_t rows = A.rows;
     int nout = ((camax + 31) / 32) * ((cbmax + 31) / 32);
-    int64_t want = std::max<int64_t>(1, 2048 / std::max(1, nt * nout));
+    int64_t want = std::max<int64_t>(1, 512 / std::max(1, nt * nout));
+    want = std::min<int64_t>(want, std::max<int64_t>(1, rows / 256));
     int64_t cap = (int64_t)(gram_ws_bytes / ((size_t)nt * camax * cbmax * esz));
     if (cap < 1) throw DeviceError("gram workspace too small");
     int64_t nch = std::min<int64_t>(std::max<int64_t>(want, 1), cap);
@@ -226,7 +227,7 @@ void Engine::r_factor(const int* dlist, int nt, const BlockList& A, int cmax, co
     c.list = dlist;
     c.cdim = cdims;
     c.cmul = cmul;
-    c.c = cfixed;
+    c.c = cfixed > 0 ? cfixed : cmax;   // with cdims: the maximum, used to size the launch
     c.G = gdd.p;
     c.strideG = (int64_t)cmax * cmax;
     c.ldG = cmax;
@@ -481,7 +482,11 @@ void Engine::size_for(int tiles)
     Csm.alloc(t * K * 3 * r); Tsm.alloc(t * 9 * r * r);
     Qt.alloc(t * K * K); Upp.alloc(t * r * r); Ucoef.alloc(t * K * r); X0c.alloc(t * K * r);
     xi.alloc(t * 3 * r); nrm2.alloc(t * 3 * r); xi_out.alloc(t * 3 * r);
-    mask.alloc(t); cdim.alloc(3 * t); d_list.alloc(t); d_list2.alloc(t); d_jobsrc.alloc(t);
+    mask.alloc(t); cdim.alloc(3 * t); d_list.alloc(t);
+    d_cdimt.alloc(t); d_pcols.alloc(t);
+    lob_it.assign(t, 0);
+    lob_sigma.assign(t, 0.0);
+    h_zt.assign(t, zmake(0.0, 0.0)); d_list2.alloc(t); d_jobsrc.alloc(t);
     d_z.alloc(t);
     const size_t J = t * B;
     j_tile.alloc(J); j_z.alloc(J); j_G.alloc(J * K * r);
@@ -502,162 +507,13 @@ void Engine::size_for(int tiles)
         Dinv.alloc(t * n * PRE_NB); T1p.alloc(t * n * PRE_NB); pvec.alloc(t * 2 * n); d_zdag.alloc(t);
         zgemm_ws.alloc(std::max<size_t>((size_t)32 << 20, t * (size_t)n * r * 16));
     }
+    d_listK.alloc(t); d_listI.alloc(t);
+    usek.assign(t, 1);
     zdag.assign(t, zmake(0.0, 0.0));
     gam.assign(t, 0.0);
     has_prec.assign(t, 0);
     h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r)); h_nrm2.alloc(t * 3 * r);
     h_small.alloc(t * 4 + 8); h_C.alloc(t * K * r + 8); h_list.alloc(t + 1); h_z.alloc(t + J);
-}
-
-// ---------------------------------------------------------------------------
-// LOBPCG-SVD (supplement, Alg. SM1.1) on C(z) for every tile in L, block size
-// r, r_v = 1, preconditioner K = I.  The start block is S[:, 0:r] of each
-// tile; on return S[:, 0:r] holds X and sigma[i] the smallest Ritz value of
-// tile L[i].
-void Engine::lobpcg(const std::vector<int>& Lin, std::vector<double>& sigma, std::vector<int>& iters,
-                    std::vector<int>& okv, uint64_t seed)
-{
-    const int nt0 = (int)Lin.size();
-    sigma.assign(nt0, 0.0);
-    iters.assign(nt0, 0);
-    okv.assign(nt0, 0);
-    if (nt0 == 0) return;
-    std::vector<int> L = Lin;
-    std::vector<int> pos(T, -1);
-    for (int i = 0; i < nt0; ++i) pos[L[i]] = i;
-    upload_list(L, d_list);
-    const int64_t sS = (int64_t)n * 3 * r, sC = (int64_t)m * 3 * r;
-    const int r3 = 3 * r;
-    // X0 orthonormal
-    orthonormalize(L, d_list.p, S.p, sS, n, n, r, nullptr, 0, seed);
-    // CX0, R0, svd -> X1
-    apply(false, d_list.p, (int)L.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
-    BlockList Lcx = bl_empty(m);
-    bl_add(Lcx, CS.p, sC, m, r, nullptr, 0);
-    r_factor(d_list.p, (int)L.size(), Lcx, r, nullptr, 0, r, Rsm.p, (int64_t)9 * r * r, r3);
-    auto set_cdim = [&](int c) { return cdim.p + (size_t)T * (c / r - 1); };
-    RRArgs ra;
-    memset(&ra, 0, sizeof(ra));
-    ra.cdim = set_cdim(r);
-    ra.r = r;
-    ra.max_sweeps = 40;
-    ra.R = Rsm.p;
-    ra.strideR = (int64_t)9 * r * r;
-    ra.ldR = r3;
-    ra.GX = GX.p;
-    ra.GP = GP.p;
-    ra.strideGX = (int64_t)9 * r * r;
-    ra.ldGX = r3;
-    ra.xi = xi.p;
-    ra.ldxi = r3;
-    ra.status = nullptr;
-    ra.list = d_list.p;
-    launch_rr_hl(ra, (int)L.size(), r, st);
-    {
-        BlockList Ls = bl_empty(n);
-        bl_add(Ls, S.p, sS, n, r, nullptr, 0);
-        gemm_ts(d_list.p, (int)L.size(), Ls, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
-        gemm_ts(d_list.p, (int)L.size(), Lcx, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p, sC, m, m, 1.0,
-                0.0);
-        launch_copy_cols(d_list.p, (int)L.size(), Sn.p, sS, n, S.p, sS, n, n, r, st);
-        launch_copy_cols(d_list.p, (int)L.size(), CSn.p, sC, m, CS.p, sC, m, m, r, st);
-    }
-    auto residual = [&](const int* dl, int nt) {
-        apply(true, dl, nt, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r, d_z.p);
-        launch_resid_xi(dl, nt, Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
-    };
-    residual(d_list.p, (int)L.size());
-    bool hasP = false;
-    const double nC = op.normC;
-    std::vector<double> hz_abs(T, 0.0);
-    {
-        HIPCHK(hipMemcpyAsync(h_z.p, d_z.p, sizeof(zd) * T, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (int t = 0; t < T; ++t) hz_abs[t] = sqrt(zabs2(h_z[t]));
-    }
-    const int maxit = P.max_iters;
-    // floor of eq. (tolSVD): the residual C(z)^*(C(z) x) - xi^2 x is itself
-    // computed with an error of order sqrt(n) eps ||C(z)||^2, so a floor of
-    // exactly eps ||C(z)||^2 can be out of reach; the constant scales with it
-    const double floor_c = std::max(16.0, 4.0 * sqrt((double)n));
-    for (int it = 1; it <= maxit && !L.empty(); ++it) {
-        const int nt = (int)L.size();
-        stats.lobpcg_iters += nt;
-        // W <- K^{-1} W, into S[:, r:2r]
-        if (use_prec) precond_apply(d_list.p, nt, Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
-        else launch_copy_cols(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r, st);
-        BlockList Lxp = bl_empty(n);
-        bl_add(Lxp, S.p, sS, n, r, nullptr, 0);
-        if (hasP) bl_add(Lxp, S.p + (size_t)2 * n * r, sS, n, r, nullptr, 0);
-        orthonormalize(L, d_list.p, S.p + (size_t)n * r, sS, n, n, r, &Lxp, hasP ? 2 * r : r,
-                       seed + 1000003ull * it);
-        apply(false, d_list.p, nt, S.p + (size_t)n * r, sS, n, CS.p + (size_t)m * r, sC, m, r, d_z.p);
-        const int c = hasP ? 3 * r : 2 * r;
-        BlockList Lcs = bl_empty(m);
-        bl_add(Lcs, CS.p, sC, m, c, nullptr, 0);
-        r_factor(d_list.p, nt, Lcs, c, nullptr, 0, c, Rsm.p, (int64_t)9 * r * r, r3);
-        ra.cdim = set_cdim(c);
-        ra.list = d_list.p;
-        launch_rr_hl(ra, nt, c, st);
-        BlockList Ls = bl_empty(n);
-        bl_add(Ls, S.p, sS, n, c, nullptr, 0);
-        gemm_ts(d_list.p, nt, Ls, c, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
-        gemm_ts(d_list.p, nt, Ls, c, GP.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p + (size_t)n * r, sS, n, n, 1.0,
-                0.0);
-        gemm_ts(d_list.p, nt, Lcs, c, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p, sC, m, m, 1.0, 0.0);
-        gemm_ts(d_list.p, nt, Lcs, c, GP.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p + (size_t)m * r, sC, m, m,
-                1.0, 0.0);
-        launch_copy_cols(d_list.p, nt, Sn.p, sS, n, S.p, sS, n, n, r, st);
-        launch_copy_cols(d_list.p, nt, Sn.p + (size_t)n * r, sS, n, S.p + (size_t)2 * n * r, sS, n, n, r, st);
-        launch_copy_cols(d_list.p, nt, CSn.p, sC, m, CS.p, sC, m, m, r, st);
-        launch_copy_cols(d_list.p, nt, CSn.p + (size_t)m * r, sC, m, CS.p + (size_t)2 * m * r, sC, m, m, r, st);
-        hasP = true;
-        residual(d_list.p, nt);
-        BlockList Lw = bl_empty(n);
-        bl_add(Lw, Wres.p, (int64_t)n * r, n, r, nullptr, 0);
-        colnorm2(d_list.p, nt, Lw, r, nrm2.p, r3);
-        HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_xi.p, xi.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        auto passes = [&](int t) {
-            double nz = nC + hz_abs[t];
-            double x0 = h_xi[(size_t)t * r3];
-            double w0 = sqrt(std::max(0.0, h_nrm2[(size_t)t * r3]));
-            return w0 <= std::max(P.eta_svd * nz * x0, floor_c * nz * nz * EPSM) || x0 <= P.eta_abs * nz;
-        };
-        std::vector<int> cand;
-        for (int t : L) if (passes(t)) cand.push_back(t);
-        std::vector<char> fin(T, 0);
-        if (!cand.empty()) {
-            // explicit recomputation of C(z) X before accepting (the implicit
-            // updates of C X drift)
-            upload_list(cand, d_list2);
-            apply(false, d_list2.p, (int)cand.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
-            residual(d_list2.p, (int)cand.size());
-            colnorm2(d_list2.p, (int)cand.size(), Lw, r, nrm2.p, r3);
-            HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            for (int t : cand) if (passes(t)) fin[t] = 1;
-        }
-        std::vector<int> L2;
-        for (int t : L) {
-            if (fin[t]) {
-                sigma[pos[t]] = h_xi[(size_t)t * r3];
-                iters[pos[t]] = it;
-                okv[pos[t]] = 1;
-            } else if (it == maxit) {
-                sigma[pos[t]] = h_xi[(size_t)t * r3];
-                iters[pos[t]] = it;
-                okv[pos[t]] = 0;
-            } else {
-                L2.push_back(t);
-            }
-        }
-        if (L2.size() != L.size()) {
-            L.swap(L2);
-            if (!L.empty()) upload_list(L, d_list);
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------

@@ -221,182 +221,216 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     bool any_uncert = false;
     const int64_t sS = (int64_t)n * 3 * r;
     uint64_t round_seed = P.seed;
+    std::vector<double> h_xi_keep;
     double t_ritz = 0, t_lob = 0, t_upd = 0;
     auto now = [] { return std::chrono::steady_clock::now(); };
     auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b2) {
         return std::chrono::duration<double, std::milli>(b2 - a).count();
     };
+    // tile states: 0 idle (next point needs its Ritz test), 1 in LOBPCG, 2 done
+    std::vector<int> state(T, 0);
+    for (int t = 0; t < T; ++t) if (tiles[t].done()) state[t] = 2;
+    uint64_t step_seed = P.seed ^ 0x9e3779b97f4a7c15ull;
+    int64_t loops = 0;
     while (true) {
-        std::vector<int> active;
-        for (int t = 0; t < T; ++t) if (!tiles[t].done()) active.push_back(t);
-        if (active.empty()) break;
-        stats.rounds++;
-        std::vector<int> R, Rsrc;      // tiles to refine, job index of their Ritz vectors (-1: none)
+        ++loops;
+        // ---- A. idle tiles: Ritz test on their next window of points
+        std::vector<int> idle;
+        for (int t = 0; t < T; ++t) if (state[t] == 0) idle.push_back(t);
+        std::vector<int> R, Rsrc;   // tiles that start a refinement, job of their Ritz vectors (-1: none)
         auto t0 = now();
-        if (P.recycle) {
-            // ---- Ritz test of the next window of every tile with a nonempty store
-            std::vector<int> jt;
-            std::vector<int> jp;
-            for (int t : active) {
-                if (tiles[t].k == 0) continue;
-                size_t e = std::min(tiles[t].order.size(), tiles[t].cursor + (size_t)B);
-                for (size_t c = tiles[t].cursor; c < e; ++c) { jt.push_back(t); jp.push_back(tiles[t].order[c]); }
-            }
-            const int nj = (int)jt.size();
-            if (nj > 0) {
-                h_small.alloc((size_t)nj * 2 + 8);
-                h_z.alloc((size_t)nj + T + 8);
-                int* hjt = (int*)h_small.p;
-                double* hn = (double*)(h_small.p + nj);
-                for (int j = 0; j < nj; ++j) {
-                    hjt[j] = jt[j];
-                    h_z[j] = zs[jp[j]];
-                    hn[j] = nC + sqrt(zabs2(zs[jp[j]]));
+        if (!idle.empty()) {
+            stats.rounds++;
+            if (P.recycle) {
+                std::vector<int> jt, jp;
+                for (int t : idle) {
+                    if (tiles[t].k == 0) continue;
+                    size_t e = std::min(tiles[t].order.size(), tiles[t].cursor + (size_t)B);
+                    for (size_t c = tiles[t].cursor; c < e; ++c) { jt.push_back(t); jp.push_back(tiles[t].order[c]); }
                 }
-                HIPCHK(hipMemcpyAsync(j_tile.p, hjt, sizeof(int) * nj, hipMemcpyHostToDevice, st));
-                HIPCHK(hipMemcpyAsync(j_z.p, h_z.p, sizeof(zd) * nj, hipMemcpyHostToDevice, st));
-                HIPCHK(hipMemcpyAsync(j_nrm.p, hn, sizeof(double) * nj, hipMemcpyHostToDevice, st));
-                RitzArgs ra;
-                memset(&ra, 0, sizeof(ra));
-                ra.njobs = nj;
-                ra.job_tile = j_tile.p;
-                ra.kdim = d_k.p;
-                ra.z = j_z.p;
-                ra.nrm = j_nrm.p;
-                ra.RA = sRA.p;
-                ra.strideRA = (int64_t)4 * K * K;
-                ra.ldRA = 2 * K;
-                ra.Rres = sRres.p;
-                ra.strideRres = (int64_t)16 * K * K;
-                ra.ldRres = 4 * K;
-                ra.nres = 4;
-                ra.nv = 1;
-                ra.ng = r;
-                ra.max_sweeps = 40;
-                ra.mode = 0;
-                ra.eta = P.eta;
-                ra.floor_c = std::max(16.0, 4.0 * sqrt((double)n));
-                ra.eta_abs = P.eta_abs;
-                ra.xi = j_xi.p;
-                ra.res = j_res.p;
-                ra.ldxi = 1;
-                ra.Gout = j_G.p;
-                ra.strideG = (int64_t)K * r;
-                ra.ldG = K;
-                ra.accept = j_acc.p;
-                int pi = prof.begin(st, 2, 0.0, 0.0);
-                launch_ritz(ra, K, st);
-                prof.end(st, pi);
-                HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpyAsync(h_acc.p, j_acc.p, nj, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipMemcpyAsync(h_xi.p, j_xi.p, sizeof(double) * nj, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-            }
-            int j = 0;
-            for (int t : active) {
-                if (tiles[t].k == 0) { R.push_back(t); Rsrc.push_back(-1); continue; }
-                size_t e = std::min(tiles[t].order.size(), tiles[t].cursor + (size_t)B);
-                size_t w = e - tiles[t].cursor;
-                bool rejected = false;
-                for (size_t c = 0; c < w; ++c, ++j) {
-                    if (rejected) continue;
-                    if (h_acc[j]) {
-                        int pt = tiles[t].order[tiles[t].cursor];
-                        sig[pt] = h_xi[j];
-                        fl[pt] |= PS_FLAG_ACCEPTED;
-                        stats.accepted++;
-                        tiles[t].cursor++;
-                    } else {
-                        rejected = true;
-                        R.push_back(t);
-                        Rsrc.push_back(j);
+                const int nj = (int)jt.size();
+                if (nj > 0) {
+                    h_small.alloc((size_t)nj * 2 + 8);
+                    h_z.alloc((size_t)nj + T + 8);
+                    int* hjt = (int*)h_small.p;
+                    double* hn = (double*)(h_small.p + nj);
+                    for (int j = 0; j < nj; ++j) {
+                        hjt[j] = jt[j];
+                        h_z[j] = zs[jp[j]];
+                        hn[j] = nC + sqrt(zabs2(zs[jp[j]]));
                     }
+                    HIPCHK(hipMemcpyAsync(j_tile.p, hjt, sizeof(int) * nj, hipMemcpyHostToDevice, st));
+                    HIPCHK(hipMemcpyAsync(j_z.p, h_z.p, sizeof(zd) * nj, hipMemcpyHostToDevice, st));
+                    HIPCHK(hipMemcpyAsync(j_nrm.p, hn, sizeof(double) * nj, hipMemcpyHostToDevice, st));
+                    RitzArgs ra;
+                    memset(&ra, 0, sizeof(ra));
+                    ra.njobs = nj;
+                    ra.job_tile = j_tile.p;
+                    ra.kdim = d_k.p;
+                    ra.z = j_z.p;
+                    ra.nrm = j_nrm.p;
+                    ra.RA = sRA.p;
+                    ra.strideRA = (int64_t)4 * K * K;
+                    ra.ldRA = 2 * K;
+                    ra.Rres = sRres.p;
+                    ra.strideRres = (int64_t)16 * K * K;
+                    ra.ldRres = 4 * K;
+                    ra.nres = 4;
+                    ra.nv = 1;
+                    ra.ng = r;
+                    ra.max_sweeps = 40;
+                    ra.mode = 0;
+                    ra.eta = P.eta;
+                    ra.floor_c = std::max(16.0, 4.0 * sqrt((double)n));
+                    ra.eta_abs = P.eta_abs;
+                    ra.normC = nC;
+                    ra.xi = j_xi.p;
+                    ra.res = j_res.p;
+                    ra.ldxi = 1;
+                    ra.Gout = j_G.p;
+                    ra.strideG = (int64_t)K * r;
+                    ra.ldG = K;
+                    ra.accept = j_acc.p;
+                    int pi = prof.begin(st, 2, 0.0, 0.0);
+                    launch_ritz(ra, K, st);
+                    prof.end(st, pi);
+                    HIPCHK(hipGetLastError());
+                    HIPCHK(hipMemcpyAsync(h_acc.p, j_acc.p, nj, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipMemcpyAsync(h_xi.p, j_xi.p, sizeof(double) * nj, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
                 }
+                h_xi_keep.assign(h_xi.p, h_xi.p + nj);
+                int j = 0;
+                for (int t : idle) {
+                    if (tiles[t].k == 0) { R.push_back(t); Rsrc.push_back(-1); continue; }
+                    size_t e = std::min(tiles[t].order.size(), tiles[t].cursor + (size_t)B);
+                    size_t w = e - tiles[t].cursor;
+                    bool rejected = false;
+                    for (size_t c = 0; c < w; ++c, ++j) {
+                        if (rejected) continue;
+                        if (h_acc[j]) {
+                            int pt = tiles[t].order[tiles[t].cursor];
+                            sig[pt] = h_xi[j];
+                            fl[pt] |= PS_FLAG_ACCEPTED;
+                            stats.accepted++;
+                            tiles[t].cursor++;
+                        } else {
+                            rejected = true;
+                            R.push_back(t);
+                            Rsrc.push_back(j);
+                        }
+                    }
+                    if (!rejected && tiles[t].done()) state[t] = 2;
+                }
+            } else {
+                for (int t : idle) { R.push_back(t); Rsrc.push_back(-1); }
             }
-        } else {
-            for (int t : active) { R.push_back(t); Rsrc.push_back(-1); }
         }
         auto t1 = now();
         t_ritz += ms(t0, t1);
-        if (R.empty()) continue;
-        // ---- start blocks: recycled Ritz vectors V g_{1:r}, or seeded random
-        std::vector<int> Rr, Rv;
-        h_small.alloc(T + 8);
-        int* hsrc = (int*)h_small.p;
-        for (size_t i = 0; i < R.size(); ++i) {
-            if (Rsrc[i] < 0) Rr.push_back(R[i]);
-            else { Rv.push_back(R[i]); hsrc[R[i]] = Rsrc[i]; }
-        }
-        if (!Rv.empty()) {
-            HIPCHK(hipMemcpyAsync(d_jobsrc.p, hsrc, sizeof(int) * T, hipMemcpyHostToDevice, st));
-            upload_list(Rv, d_list);
-            launch_gather(d_list.p, (int)Rv.size(), d_jobsrc.p, j_G.p, (int64_t)K * r, X0c.p, (int64_t)K * r,
-                          (int64_t)K * r, st);
-            BlockList Lv = bl_empty(n);
-            bl_add(Lv, sV.p, (int64_t)n * K, n, 0, d_k.p, 1);
-            gemm_ts(d_list.p, (int)Rv.size(), Lv, K, X0c.p, (int64_t)K * r, K, nullptr, 0, r, S.p, sS, n, n, 1.0,
-                    0.0);
-        }
-        if (!Rr.empty()) {
-            upload_list(Rr, d_list);
-            round_seed = round_seed * 6364136223846793005ull + 1442695040888963407ull;
-            launch_randfill(d_list.p, (int)Rr.size(), S.p, sS, n, n, r, nullptr, round_seed, st);
-        }
-        // base preconditioner: build at the first refined point of a tile and
-        // rebuild at z when the Weyl bound of eq. (tauRecycle) on the largest
-        // pencil eigenvalue, (sqrt(lambda_n^dag) + gamma |z - z_dag|)^2 with
-        // lambda_n^dag <= 1 for F^* F = N(z_dag) + delta I, exceeds tau_max.
-        // Without the coarse (two-level) correction nothing lifts the small
-        // end of the pencil spectrum, which Weyl's inequality bounds below by
-        // (1 - gamma |z - z_dag|)^2; the same rule is then applied to the
-        // condition number bound ((1 + g)/(1 - g))^2 <= tau_max.
-        if (use_prec) {
-            std::vector<int> Rb;
-            for (int t : R) {
-                zd z = zs[tiles[t].order[tiles[t].cursor]];
-                bool rebuild = !has_prec[t];
-                if (!rebuild) {
-                    double g = gam[t] * sqrt(zabs2(zsub(z, zdag[t])));
-                    double bound = (1.0 + g) * (1.0 + g);
-                    if (g >= 1.0) rebuild = true;
-                    else rebuild = bound / ((1.0 - g) * (1.0 - g)) > P.tau_max;
-                }
-                if (rebuild) {
-                    zdag[t] = z;
-                    Rb.push_back(t);
-                    fl[tiles[t].order[tiles[t].cursor]] |= PS_FLAG_REBUILD;
-                }
+        // ---- B. start LOBPCG on the newly rejected points
+        if (!R.empty()) {
+            std::vector<int> Rr, Rv;
+            h_small.alloc(T + 8);
+            int* hsrc = (int*)h_small.p;
+            for (size_t i = 0; i < R.size(); ++i) {
+                if (Rsrc[i] < 0) Rr.push_back(R[i]);
+                else { Rv.push_back(R[i]); hsrc[R[i]] = Rsrc[i]; }
             }
-            auto tp0 = now();
-            build_precond(Rb);
-            HIPCHK(hipStreamSynchronize(st));
-            stats.t_precond_ms += ms(tp0, now());
+            if (!Rv.empty()) {
+                HIPCHK(hipMemcpyAsync(d_jobsrc.p, hsrc, sizeof(int) * T, hipMemcpyHostToDevice, st));
+                upload_list(Rv, d_list);
+                launch_gather(d_list.p, (int)Rv.size(), d_jobsrc.p, j_G.p, (int64_t)K * r, X0c.p, (int64_t)K * r,
+                              (int64_t)K * r, st);
+                BlockList Lv = bl_empty(n);
+                bl_add(Lv, sV.p, (int64_t)n * K, n, 0, d_k.p, 1);
+                gemm_ts(d_list.p, (int)Rv.size(), Lv, K, X0c.p, (int64_t)K * r, K, nullptr, 0, r, S.p, sS, n, n,
+                        1.0, 0.0);
+            }
+            if (!Rr.empty()) {
+                upload_list(Rr, d_list);
+                step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
+                launch_randfill(d_list.p, (int)Rr.size(), S.p, sS, n, n, r, nullptr, step_seed, st);
+            }
+            // base preconditioner: build at the first refined point of a tile
+            // and rebuild at z when the Weyl-type bound of eq. (tauRecycle)
+            // fails; near-singular points (recycled Ritz value below
+            // rho_small ||M(z)||) have a well separated smallest singular
+            // value and run with K = I.  Without the coarse (two-level)
+            // correction nothing lifts the small end of the pencil spectrum,
+            // bounded below by (1 - gamma |z - z_dag|)^2, so the rule is applied
+            // to the condition-number bound ((1 + g)/(1 - g))^2 <= tau_max.
+            if (use_prec) {
+                std::vector<int> Rb;
+                for (size_t i = 0; i < R.size(); ++i) {
+                    const int t = R[i];
+                    zd z = zs[tiles[t].order[tiles[t].cursor]];
+                    usek[t] = 1;
+                    if (Rsrc[i] >= 0 && h_xi_keep[Rsrc[i]] <= P.rho_small * (nC + sqrt(zabs2(z)))) {
+                        usek[t] = 0;
+                        continue;
+                    }
+                    bool rebuild = !has_prec[t];
+                    if (!rebuild) {
+                        double g = gam[t] * sqrt(zabs2(zsub(z, zdag[t])));
+                        if (g >= 1.0) rebuild = true;
+                        else rebuild = (1.0 + g) * (1.0 + g) / ((1.0 - g) * (1.0 - g)) > P.tau_max;
+                    }
+                    if (rebuild) {
+                        zdag[t] = z;
+                        Rb.push_back(t);
+                        fl[tiles[t].order[tiles[t].cursor]] |= PS_FLAG_REBUILD;
+                    }
+                }
+                auto tp0 = now();
+                build_precond(Rb);
+                HIPCHK(hipStreamSynchronize(st));
+                stats.t_precond_ms += ms(tp0, now());
+            }
+            h_z.alloc((size_t)T + 8);
+            for (int t : R) h_zt[t] = zs[tiles[t].order[tiles[t].cursor]];
+            for (int t = 0; t < T; ++t) h_z[t] = h_zt[t];
+            HIPCHK(hipMemcpyAsync(d_z.p, h_z.p, sizeof(zd) * T, hipMemcpyHostToDevice, st));
+            step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
+            lob_start(R, step_seed);
+            for (int t : R) state[t] = 1;
         }
-        // current z of each refined tile
-        h_z.alloc((size_t)T + 8);
-        for (int t : R) h_z[t] = zs[tiles[t].order[tiles[t].cursor]];
-        HIPCHK(hipMemcpyAsync(d_z.p, h_z.p, sizeof(zd) * T, hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
-        std::vector<double> sg;
-        std::vector<int> its, okv;
-        lobpcg(R, sg, its, okv, round_seed ^ 0x9e3779b97f4a7c15ull);
+        // ---- C. one LOBPCG iteration for every running tile
+        std::vector<int> run;
+        for (int t = 0; t < T; ++t) if (state[t] == 1) run.push_back(t);
+        if (run.empty()) {
+            bool all = true;
+            for (int t = 0; t < T; ++t) all &= (state[t] == 2);
+            if (all) break;
+            continue;
+        }
         auto t2 = now();
-        t_lob += ms(t1, t2);
-        for (size_t i = 0; i < R.size(); ++i) {
-            int t = R[i];
+        std::vector<int> fin, okv;
+        step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
+        lob_step(run, step_seed, fin, okv);
+        auto t3 = now();
+        t_lob += ms(t1, t3) - 0.0 * ms(t1, t2);
+        // ---- D. finished tiles: record sigma, update their recycled store
+        for (size_t i = 0; i < fin.size(); ++i) {
+            int t = fin[i];
             int pt = tiles[t].order[tiles[t].cursor];
-            sig[pt] = sg[i];
+            sig[pt] = lob_sigma[t];
             fl[pt] |= PS_FLAG_REFINED;
             if (!okv[i]) { fl[pt] |= PS_FLAG_UNCERTIFIED; any_uncert = true; stats.uncertified++; }
             stats.refined++;
             tiles[t].cursor++;
         }
-        if (P.recycle) update_store(R);
-        t_upd += ms(t2, now());
-        if (P.verbose && stats.rounds % 20 == 0) {
-            fprintf(stderr, "[ps] round %lld: accepted %lld refined %lld rebuilds %lld iters %lld  %.1f s\n",
-                    (long long)stats.rounds, (long long)stats.accepted, (long long)stats.refined,
-                    (long long)stats.rebuilds, (long long)stats.lobpcg_iters, ms(t_start, now()) / 1000.0);
+        if (!fin.empty()) {
+            if (P.recycle) update_store(fin);
+            for (int t : fin) state[t] = tiles[t].done() ? 2 : 0;
+        }
+        t_upd += ms(t3, now());
+        if (P.verbose && loops % 200 == 0) {
+            int64_t done_pts = stats.accepted + stats.refined;
+            fprintf(stderr, "[ps] step %lld: points %lld/%lld accepted %lld refined %lld rebuilds %lld iters %lld  %.1f s\n",
+                    (long long)loops, (long long)done_pts, (long long)npts, (long long)stats.accepted,
+                    (long long)stats.refined, (long long)stats.rebuilds, (long long)stats.lobpcg_iters,
+                    ms(t_start, now()) / 1000.0);
             fflush(stderr);
         }
     }

@@ -1,0 +1,174 @@
+// LOBPCG-SVD (supplement, Alg. SM1.1) on C(z) = C - z S for many tiles at
+// once, written as a per-tile state machine so that the scheduler can keep
+// the batch full: tiles enter (lob_start) and leave (lob_step returns them)
+// independently.  Block size r, r_v = 1, preconditioner K = F^*F (tiles with
+// usek) or K = I.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+static const double EPSM_L = 2.220446049250313e-16;
+
+// First Rayleigh-Ritz-SVD step: X0 (S[:, 0:r]) orthonormalised, R of C(z) X0,
+// SVD R = J Xi G^*, X1 = X0 G, C X1 = (C X0) G, residual W = C^*(C X1) - X1 Xi^2.
+void Engine::lob_start(const std::vector<int>& L, uint64_t seed)
+{
+    if (L.empty()) return;
+    const int nt = (int)L.size();
+    upload_list(L, d_list);
+    const int64_t sS = (int64_t)n * 3 * r, sC = (int64_t)m * 3 * r;
+    const int r3 = 3 * r;
+    orthonormalize(L, d_list.p, S.p, sS, n, n, r, nullptr, 0, seed);
+    apply(false, d_list.p, nt, S.p, sS, n, CS.p, sC, m, r, d_z.p);
+    BlockList Lcx = bl_empty(m);
+    bl_add(Lcx, CS.p, sC, m, r, nullptr, 0);
+    r_factor(d_list.p, nt, Lcx, r, nullptr, 0, r, Rsm.p, (int64_t)9 * r * r, r3);
+    RRArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.list = d_list.p;
+    ra.cdim = cdim.p;              // preset row: r for every tile
+    ra.r = r;
+    ra.max_sweeps = 40;
+    ra.R = Rsm.p;
+    ra.strideR = (int64_t)9 * r * r;
+    ra.ldR = r3;
+    ra.GX = GX.p;
+    ra.GP = GP.p;
+    ra.strideGX = (int64_t)9 * r * r;
+    ra.ldGX = r3;
+    ra.xi = xi.p;
+    ra.ldxi = r3;
+    launch_rr_hl(ra, nt, r, st);
+    BlockList Ls = bl_empty(n);
+    bl_add(Ls, S.p, sS, n, r, nullptr, 0);
+    gemm_ts(d_list.p, nt, Ls, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
+    gemm_ts(d_list.p, nt, Lcx, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p, sC, m, m, 1.0, 0.0);
+    launch_copy_cols(d_list.p, nt, Sn.p, sS, n, S.p, sS, n, n, r, st);
+    launch_copy_cols(d_list.p, nt, CSn.p, sC, m, CS.p, sC, m, m, r, st);
+    apply(true, d_list.p, nt, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r, d_z.p);
+    launch_resid_xi(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
+    for (int t : L) lob_it[t] = 0;
+}
+
+// One iteration for every tile in L:
+//   W <- K^{-1} W; W orthonormal and orthogonal to [X P]; S = [X W P];
+//   R of C(z) S (mixed-precision Cholesky QR); SVD of R; Hetmaniuk-Lehoucq
+//   X, P; implicit C X, C P; W = C^*(C X) - X Xi^2; the test of eq. (tolSVD)
+//   on the first Ritz pair, confirmed with an explicitly recomputed C X.
+void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>& done, std::vector<int>& okv)
+{
+    done.clear();
+    okv.clear();
+    if (L.empty()) return;
+    const int nt = (int)L.size();
+    const int64_t sS = (int64_t)n * 3 * r, sC = (int64_t)m * 3 * r;
+    const int r3 = 3 * r;
+    upload_list(L, d_list);
+    // per-tile widths: S has 2r columns on a tile's first iteration, 3r after
+    {
+        h_small.alloc(2 * T + 8);
+        int* hc = (int*)h_small.p;
+        for (int t = 0; t < T; ++t) {
+            bool hasP = lob_it[t] > 0;
+            hc[t] = hasP ? 3 * r : 2 * r;
+            hc[T + t] = hasP ? r : 0;
+        }
+        HIPCHK(hipMemcpyAsync(d_cdimt.p, hc, sizeof(int) * T, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_pcols.p, hc + T, sizeof(int) * T, hipMemcpyHostToDevice, st));
+    }
+    // W <- K^{-1} W into S[:, r:2r]
+    if (use_prec) {
+        std::vector<int> Lk, Li;
+        for (int t : L) (usek[t] ? Lk : Li).push_back(t);
+        upload_list(Lk, d_listK);
+        upload_list(Li, d_listI);
+        precond_apply(d_listK.p, (int)Lk.size(), Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
+        launch_copy_cols(d_listI.p, (int)Li.size(), Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r,
+                         st);
+    } else {
+        launch_copy_cols(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r, st);
+    }
+    stats.lobpcg_iters += nt;
+    BlockList Lxp = bl_empty(n);
+    bl_add(Lxp, S.p, sS, n, r, nullptr, 0);
+    bl_add(Lxp, S.p + (size_t)2 * n * r, sS, n, 0, d_pcols.p, 1);
+    orthonormalize(L, d_list.p, S.p + (size_t)n * r, sS, n, n, r, &Lxp, 2 * r, seed);
+    apply(false, d_list.p, nt, S.p + (size_t)n * r, sS, n, CS.p + (size_t)m * r, sC, m, r, d_z.p);
+    BlockList Lcs = bl_empty(m);
+    bl_add(Lcs, CS.p, sC, m, 0, d_cdimt.p, 1);
+    r_factor(d_list.p, nt, Lcs, r3, d_cdimt.p, 1, 0, Rsm.p, (int64_t)9 * r * r, r3);
+    RRArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.list = d_list.p;
+    ra.cdim = d_cdimt.p;
+    ra.r = r;
+    ra.max_sweeps = 40;
+    ra.R = Rsm.p;
+    ra.strideR = (int64_t)9 * r * r;
+    ra.ldR = r3;
+    ra.GX = GX.p;
+    ra.GP = GP.p;
+    ra.strideGX = (int64_t)9 * r * r;
+    ra.ldGX = r3;
+    ra.xi = xi.p;
+    ra.ldxi = r3;
+    launch_rr_hl(ra, nt, r3, st);
+    BlockList Ls = bl_empty(n);
+    bl_add(Ls, S.p, sS, n, 0, d_cdimt.p, 1);
+    gemm_ts(d_list.p, nt, Ls, r3, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
+    gemm_ts(d_list.p, nt, Ls, r3, GP.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p + (size_t)n * r, sS, n, n, 1.0,
+            0.0);
+    gemm_ts(d_list.p, nt, Lcs, r3, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p, sC, m, m, 1.0, 0.0);
+    gemm_ts(d_list.p, nt, Lcs, r3, GP.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p + (size_t)m * r, sC, m, m, 1.0,
+            0.0);
+    launch_copy_cols(d_list.p, nt, Sn.p, sS, n, S.p, sS, n, n, r, st);
+    launch_copy_cols(d_list.p, nt, Sn.p + (size_t)n * r, sS, n, S.p + (size_t)2 * n * r, sS, n, n, r, st);
+    launch_copy_cols(d_list.p, nt, CSn.p, sC, m, CS.p, sC, m, m, r, st);
+    launch_copy_cols(d_list.p, nt, CSn.p + (size_t)m * r, sC, m, CS.p + (size_t)2 * m * r, sC, m, m, r, st);
+    for (int t : L) lob_it[t]++;
+    auto residual = [&](const int* dl, int k) {
+        apply(true, dl, k, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r, d_z.p);
+        launch_resid_xi(dl, k, Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
+    };
+    residual(d_list.p, nt);
+    BlockList Lw = bl_empty(n);
+    bl_add(Lw, Wres.p, (int64_t)n * r, n, r, nullptr, 0);
+    colnorm2(d_list.p, nt, Lw, r, nrm2.p, r3);
+    HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_xi.p, xi.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double nC = op.normC;
+    // floor of eq. (tolSVD): the residual C(z)^*(C(z) x) - xi^2 x is itself
+    // computed with an error of order sqrt(n) eps ||C(z)||^2, so a floor of
+    // exactly eps ||C(z)||^2 can be out of reach; the constant scales with it
+    const double floor_c = std::max(16.0, 4.0 * sqrt((double)n));
+    auto passes = [&](int t) {
+        double nz = nC + sqrt(zabs2(h_zt[t]));
+        double x0 = h_xi[(size_t)t * r3];
+        double w0 = sqrt(std::max(0.0, h_nrm2[(size_t)t * r3]));
+        return w0 <= std::max(P.eta_svd * nz * x0, floor_c * nz * nz * EPSM_L) || x0 <= P.eta_abs * nC;
+    };
+    std::vector<int> cand;
+    for (int t : L) if (passes(t)) cand.push_back(t);
+    std::vector<char> fin(T, 0);
+    if (!cand.empty()) {
+        // explicit recomputation of C(z) X before accepting (the implicit
+        // updates of C X drift)
+        upload_list(cand, d_list2);
+        apply(false, d_list2.p, (int)cand.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
+        residual(d_list2.p, (int)cand.size());
+        colnorm2(d_list2.p, (int)cand.size(), Lw, r, nrm2.p, r3);
+        HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int t : cand) if (passes(t)) fin[t] = 1;
+    }
+    for (int t : L) {
+        if (fin[t] || lob_it[t] >= P.max_iters) {
+            lob_sigma[t] = h_xi[(size_t)t * r3];
+            done.push_back(t);
+            okv.push_back(fin[t] ? 1 : 0);
+        }
+    }
+}

@@ -10,6 +10,7 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
                    int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
                    double beta, int upper, int tri)
 {
+    if (nt <= 0 || M <= 0 || N <= 0) return;
     ZgemmArgs a;
     memset(&a, 0, sizeof(a));
     a.list = dl;
@@ -53,6 +54,7 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
 // K^{-1} W for the tiles in dl: Y = F^{-1} (F^{-*} W), W and Y n x r per tile
 void Engine::precond_apply(const int* dl, int nt, const zd* W, int64_t ws, zd* Y, int64_t ys)
 {
+    if (nt <= 0) return;
     const int64_t nn = n * n;
     stats.sv_F += (int64_t)2 * nt * r;
     zgemm(dl, nt, n, r, n, FinvH.p, n, nn, 0, W, n, ws, Tn2.p, n, (int64_t)n * r, 1.0, 0.0, 0, 2);

@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(NT) k_ritz(RitzArgs a)
     const zd* RA = a.RA + (size_t)tile * a.strideRA;
     zd* B = sm;                       // 2k x k, ld = m2
     // B(z) = R_A[:, :k] - z R_A[:, k:2k]
-    for (int idx = tid; idx < m2 * k; idx += NT) {
+    for (int idx = tid; idx < m2 * k; idx += blockDim.x) {
         int i = idx % m2, j = idx / m2;
         zd r1 = RA[i + (size_t)j * a.ldRA];
         zd r2 = RA[i + (size_t)(k + j) * a.ldRA];
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(NT) k_ritz(RitzArgs a)
     const int ng = min(a.ng, k);
     // right vectors out
     zd* Gout = a.Gout + (size_t)job * a.strideG;
-    for (int idx = tid; idx < k * ng; idx += NT) {
+    for (int idx = tid; idx < k * ng; idx += blockDim.x) {
         int i = idx % k, c = idx / k;
         Gout[i + (size_t)c * a.ldG] = G[i + perm[c] * k];
     }
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(NT) k_ritz(RitzArgs a)
         const int col = perm[v];
         const double xi = sv[col];
         double acc = 0.0;
-        for (int i = tid; i < rows; i += NT) {
+        for (int i = tid; i < rows; i += blockDim.x) {
             zd s = zmake(0.0, 0.0);
             // R_res upper triangular: row i, columns c >= i (global column index c = blk*k + j)
             for (int c = i; c < rows; ++c) {
@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(NT) k_ritz(RitzArgs a)
         if (a.mode == 0) {
             double xi0 = sv[perm[0]];
             double thr = fmax(a.eta * xi0 * nrm, a.floor_c * nrm * nrm * 2.220446049250313e-16);
-            acc = (sres[0] <= thr) || (xi0 <= a.eta_abs * nrm);
+            acc = (sres[0] <= thr) || (xi0 <= a.eta_abs * a.normC);
         } else {
             for (int v = 0; v < nv; ++v) acc &= (sres[v] <= a.eta * nrm);
         }
@@ -348,7 +348,7 @@ __global__ void __launch_bounds__(NT) k_chol_dd(CholArgs a)
     const int tid = threadIdx.x;
     if (c <= 0) return;
     double dmax = 0;
-    for (int i = tid; i < c; i += NT) dmax = fmax(dmax, G[i + (size_t)i * ldg].x.hi);
+    for (int i = tid; i < c; i += blockDim.x) dmax = fmax(dmax, G[i + (size_t)i * ldg].x.hi);
     dmax = block_max(dmax, red);
     const double thr = (double)c * 1e-30 * dmax;
     for (int j = 0; j < c; ++j) {
@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(NT) k_chol_dd(CholArgs a)
         __syncthreads();
         const int zr = zero_s;
         const ddv piv = piv_s;
-        for (int kk = j + tid; kk < c; kk += NT) {
+        for (int kk = j + tid; kk < c; kk += blockDim.x) {
             zdd v;
             if (zr) v = zdd_zero();
             else if (kk == j) { v.x = piv; v.y = dd_make(0.0); }
@@ -369,11 +369,11 @@ __global__ void __launch_bounds__(NT) k_chol_dd(CholArgs a)
             rowr[2 * kk + 1] = v.y;
             R[j + (size_t)kk * ldr] = zmake(v.x.hi + v.x.lo, v.y.hi + v.y.lo);
         }
-        for (int i = tid; i < j; i += NT) R[j + (size_t)i * ldr] = zmake(0.0, 0.0);
+        for (int i = tid; i < j; i += blockDim.x) R[j + (size_t)i * ldr] = zmake(0.0, 0.0);
         __syncthreads();
         if (!zr) {
             // trailing update G[kk][ll] -= conj(R[j][kk]) R[j][ll], j < kk <= ll
-            for (int kk = j + 1 + tid; kk < c; kk += NT) {
+            for (int kk = j + 1 + tid; kk < c; kk += blockDim.x) {
                 zdd rk; rk.x = rowr[2 * kk]; rk.y = rowr[2 * kk + 1];
                 for (int ll = kk; ll < c; ++ll) {
                     zdd rl; rl.x = rowr[2 * ll]; rl.y = rowr[2 * ll + 1];
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(NT) k_rr_hl(RRArgs a)
     zd* G = T + c * c;     // c x c
     zd* Y = G + c * c;     // (c - r) x r
     zd* Q = Y + (c - r) * r;
-    for (int idx = tid; idx < c * c; idx += NT) {
+    for (int idx = tid; idx < c * c; idx += blockDim.x) {
         int i = idx % c, j = idx / c;
         T[i + j * c] = (i <= j) ? Rin[i + (size_t)j * a.ldR] : zmake(0.0, 0.0);
     }
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(NT) k_rr_hl(RRArgs a)
     wg_sort_perm(sv, c, perm);
     zd* GX = a.GX + (size_t)tile * a.strideGX;
     zd* GP = a.GP + (size_t)tile * a.strideGX;
-    for (int idx = tid; idx < c * r; idx += NT) {
+    for (int idx = tid; idx < c * r; idx += blockDim.x) {
         int i = idx % c, j = idx / c;
         GX[i + (size_t)j * a.ldGX] = G[i + perm[j] * c];
     }
@@ -429,14 +429,14 @@ __global__ void __launch_bounds__(NT) k_rr_hl(RRArgs a)
     const int nc = c - r;
     if (nc < r) {
         // no complement to choose from (first step of the iteration)
-        for (int idx = tid; idx < c * r; idx += NT) {
+        for (int idx = tid; idx < c * r; idx += blockDim.x) {
             int i = idx % c, j = idx / c;
             GP[i + (size_t)j * a.ldGX] = zmake(0.0, 0.0);
         }
         return;
     }
     // Y = (G_c[:r, :])^*  ((c - r) x r): Y[i][j] = conj(G[j, perm[r + i]])
-    for (int idx = tid; idx < nc * r; idx += NT) {
+    for (int idx = tid; idx < nc * r; idx += blockDim.x) {
         int i = idx % nc, j = idx / nc;
         Y[i + j * nc] = zconj(G[j + perm[r + i] * c]);
     }
@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(NT) k_rr_hl(RRArgs a)
     wg_house_qr(Y, nc, nc, r, vhead, red);
     wg_house_q(Y, nc, nc, r, vhead, Q, nc, r);
     // G_P = G_c Q  (c x r)
-    for (int idx = tid; idx < c * r; idx += NT) {
+    for (int idx = tid; idx < c * r; idx += blockDim.x) {
         int i = idx % c, j = idx / c;
         zd s = zmake(0.0, 0.0);
         for (int l = 0; l < nc; ++l) zfma(s, G[i + perm[r + l] * c], Q[l + j * nc]);
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(NT) k_svqb(SvqbArgs a)
     const zd* Rin = a.R + (size_t)tile * a.strideR;
     zd* T = sm;
     zd* G = T + r * r;
-    for (int idx = tid; idx < r * r; idx += NT) {
+    for (int idx = tid; idx < r * r; idx += blockDim.x) {
         int i = idx % r, j = idx / r;
         T[i + j * r] = (i <= j) ? Rin[i + (size_t)j * a.ldR] : zmake(0.0, 0.0);
     }
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(NT) k_svqb(SvqbArgs a)
     double smax = 0;
     for (int j = 0; j < r; ++j) smax = fmax(smax, sv[j]);
     zd* Tout = a.T + (size_t)tile * a.strideT;
-    for (int idx = tid; idx < r * r; idx += NT) {
+    for (int idx = tid; idx < r * r; idx += blockDim.x) {
         int i = idx % r, j = idx / r;
         double s = sv[j];
         zd v = (s > a.drop * smax && s > 0.0) ? zscale(G[i + j * r], 1.0 / s) : zmake(0.0, 0.0);
@@ -522,29 +522,29 @@ __global__ void __launch_bounds__(NT) k_rotations(RotArgs a)
     zd* Upp = Tmp + kk * 2 * r;        // r x r
     const zd* U = a.U + (size_t)tile * a.strideU;
     const zd* Uin = a.Upp + (size_t)tile * a.strideUpp;
-    for (int idx = tid; idx < kk * kk; idx += NT) {
+    for (int idx = tid; idx < kk * kk; idx += blockDim.x) {
         int i = idx % kk, j = idx / kk;
         Qt[i + j * kk] = zmake(i == j ? 1.0 : 0.0, 0.0);
     }
-    for (int idx = tid; idx < r * r; idx += NT) {
+    for (int idx = tid; idx < r * r; idx += blockDim.x) {
         int i = idx % r, j = idx / r;
         Upp[i + j * r] = Uin[i + (size_t)j * a.ldUpp];
     }
     __syncthreads();
     for (int jj = 0; jj < q; ++jj) {
-        for (int idx = tid; idx < 2 * r * r; idx += NT) {
+        for (int idx = tid; idx < 2 * r * r; idx += blockDim.x) {
             int i = idx % (2 * r), j = idx / (2 * r);
             Y[i + j * 2 * r] = (i < r) ? Upp[i + j * r] : U[(jj * r + i - r) + (size_t)j * a.ldU];
         }
         __syncthreads();
         wg_house_qr(Y, 2 * r, 2 * r, r, vhead, red);
         wg_house_q(Y, 2 * r, 2 * r, r, vhead, Ql, 2 * r, 2 * r);
-        for (int idx = tid; idx < r * r; idx += NT) {
+        for (int idx = tid; idx < r * r; idx += blockDim.x) {
             int i = idx % r, j = idx / r;
             Upp[i + j * r] = (i <= j) ? Y[i + j * 2 * r] : zmake(0.0, 0.0);
         }
         // Qt[:, cols] <- Qt[:, cols] Ql with cols = [new block, block jj]
-        for (int idx = tid; idx < kk * 2 * r; idx += NT) {
+        for (int idx = tid; idx < kk * 2 * r; idx += blockDim.x) {
             int i = idx % kk, j = idx / kk;
             zd s = zmake(0.0, 0.0);
             for (int l = 0; l < 2 * r; ++l) {
@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(NT) k_rotations(RotArgs a)
             Tmp[i + j * kk] = s;
         }
         __syncthreads();
-        for (int idx = tid; idx < kk * 2 * r; idx += NT) {
+        for (int idx = tid; idx < kk * 2 * r; idx += blockDim.x) {
             int i = idx % kk, j = idx / kk;
             int col = (j < r) ? (q * r + j) : (jj * r + j - r);
             Qt[i + col * kk] = Tmp[i + j * kk];
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(NT) k_rotations(RotArgs a)
         __syncthreads();
     }
     zd* Qo = a.Qt + (size_t)tile * a.strideQt;
-    for (int idx = tid; idx < kk * kk; idx += NT) {
+    for (int idx = tid; idx < kk * kk; idx += blockDim.x) {
         int i = idx % kk, j = idx / kk;
         Qo[i + (size_t)j * a.ldQt] = Qt[i + j * kk];
     }
@@ -578,22 +578,25 @@ void launch_ritz(const RitzArgs& a, int kmax, hipStream_t s)
     size_t sm = ritz_smem(kmax);
     hipLaunchKernelGGL(k_ritz, dim3(a.njobs), dim3(NT), sm, s, a);
 }
+// Problems of dimension <= 32 run on a single wavefront: their sweeps are
+// barrier-bound, and a one-wave workgroup makes every barrier nearly free.
 void launch_chol_dd(const CholArgs& a, int nb, hipStream_t s)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_chol_dd, dim3(nb), dim3(NT), 0, s, a);
+    int th = (a.c <= 32) ? 64 : NT;   // a.c: the (maximum) dimension
+    hipLaunchKernelGGL(k_chol_dd, dim3(nb), dim3(th), 0, s, a);
 }
 void launch_rr_hl(const RRArgs& a, int nb, int cmax, hipStream_t s)
 {
     if (nb <= 0) return;
     size_t sm = (size_t)(2 * cmax * cmax + 2 * cmax * a.r) * sizeof(zd);
-    hipLaunchKernelGGL(k_rr_hl, dim3(nb), dim3(NT), sm, s, a);
+    hipLaunchKernelGGL(k_rr_hl, dim3(nb), dim3(cmax <= 32 ? 64 : NT), sm, s, a);
 }
 void launch_svqb(const SvqbArgs& a, int nb, hipStream_t s)
 {
     if (nb <= 0) return;
     size_t sm = (size_t)(2 * a.r * a.r) * sizeof(zd);
-    hipLaunchKernelGGL(k_svqb, dim3(nb), dim3(NT), sm, s, a);
+    hipLaunchKernelGGL(k_svqb, dim3(nb), dim3(a.r <= 32 ? 64 : NT), sm, s, a);
 }
 void launch_rotations(const RotArgs& a, int nb, int qmax, hipStream_t s)
 {

@@ -16,7 +16,8 @@ struct RitzArgs {
     int nv, ng, max_sweeps, mode;
     double eta;
     double floor_c;        // floor of tolC: floor_c * eps * nrm^2
-    double eta_abs;        // accept when xi_0 <= eta_abs * nrm (upper-bound certificate)
+    double eta_abs;        // accept when xi_0 <= eta_abs * normC (upper-bound certificate)
+    double normC;
     double* xi; double* res; int ldxi;     // per job nv values
     zd* Gout; int64_t strideG; int ldG;    // per job k x ng right vectors
     uint8_t* accept;
