@@ -110,12 +110,28 @@ typedef struct {
     int32_t profile;    /* 1: time the operator-apply and matrix-core GEMM
                            kernels with HIP events (fills the k_* stats) */
     int32_t verbose;    /* 1: progress lines on stderr */
+    double tol_abs;     /* certification half-width tau as a fraction of
+                           ||C||_2 (default 5e-9): a refinement still running
+                           after esc_iters iterations is accepted when
+                           N(z) - mu I, mu = (xi - tau)^2 + rounding slack, is
+                           positive definite (then xi - tau <= sigma_min <= xi);
+                           0 disables (dense C with precond = 1 only) */
+    int32_t esc_iters;  /* escalation period of slow refinements: the
+                           inertia test above, a shifted preconditioner
+                           N(z) - (xi - 64 tau)^2 I, or an exact site at z
+                           (default 30; 0 disables) */
+    int32_t lipschitz;  /* 1 (default): after the sweep, points whose value
+                           exceeds a grid neighbour's by more than their
+                           distance (sigma_min is 1-Lipschitz, computed values
+                           are upper bounds) are refined again from a random
+                           start */
 } ps_params;
 
 typedef struct {
     int64_t points;        /* grid points evaluated */
     int64_t accepted;      /* accepted by the recycled Ritz test (tolC) */
-    int64_t refined;       /* refined by LOBPCG-SVD (recycling points) */
+    int64_t refined;       /* LOBPCG-SVD refinements (recycling points, and
+                              points refined again by the Lipschitz pass) */
     int64_t uncertified;   /* LOBPCG hit max_iters */
     int64_t lobpcg_iters;  /* singular LOBPCG iterations, summed over points */
     int64_t proj_accepted; /* projection Ritz vectors accepted (tolTz) */
@@ -125,6 +141,8 @@ typedef struct {
     int64_t mv_M;          /* operator column-applies of C or C^* */
     int64_t sv_F;          /* column solves / applies with F^{-1}, F^{-*} */
     int64_t rounds;        /* scheduler rounds */
+    int64_t certified;     /* refinements ended by the inertia test (tol_abs) */
+    int64_t lipschitz_redo;/* points refined again by the Lipschitz pass */
     double t_total_ms;     /* wall time of ps_eval */
     double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
     /* with profile = 1: event-timed kernel classes (launches, device ms,
@@ -144,6 +162,8 @@ typedef struct {
 #define PS_FLAG_UNCERTIFIED 4u  /* LOBPCG hit the iteration cap */
 #define PS_FLAG_PROJ_REFINED 8u /* projection subspace refined here */
 #define PS_FLAG_REBUILD 16u     /* base preconditioner rebuilt here */
+#define PS_FLAG_CERTIFIED 32u   /* sigma certified by the inertia test */
+#define PS_FLAG_LIPSCHITZ 64u   /* refined again after a Lipschitz violation */
 
 void ps_default_params(ps_params* p);
 

@@ -46,13 +46,14 @@ class ps_params(ctypes.Structure):
                 ("tau_max", ctypes.c_double), ("zdag_re", ctypes.c_double), ("zdag_im", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("eta_abs", ctypes.c_double), ("rho_small", ctypes.c_double),
                 ("profile", ctypes.c_int32),
-                ("verbose", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("tol_abs", ctypes.c_double), ("esc_iters", ctypes.c_int32),
+                ("lipschitz", ctypes.c_int32)]
 
 
 class ps_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "points", "accepted", "refined", "uncertified", "lobpcg_iters", "proj_accepted",
-        "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds")] + \
+        "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds", "certified", "lipschitz_redo")] + \
         [(n, ctypes.c_double) for n in ("t_total_ms", "t_ritz_ms", "t_lobpcg_ms", "t_update_ms",
                                         "t_precond_ms")] + \
         [("k_launches", ctypes.c_int64 * 4), ("k_ms", ctypes.c_double * 4), ("k_flops", ctypes.c_double * 4),

@@ -148,20 +148,43 @@ struct Engine {
     HBuf<int> h_list;
     HBuf<zd> h_z;
 
-    // dense base preconditioner (per tile): K = F^* F, F the upper Cholesky
-    // factor of N(z_dag) + delta I; F^{-1} and F^{-*} kept explicitly
-    DBuf<zd> CtC, PN, Finv, FinvH, Dinv, T1p, pvec, d_zdag, zgemm_ws;
-    std::vector<zd> zdag;
-    std::vector<double> gam;
-    std::vector<char> has_prec;
+    // dense base preconditioner: a pool of NS sites, each K = F^* F with F the
+    // upper Cholesky factor of N(z_dag) + delta I and F^{-1} kept explicitly
+    // (Finv, one n x n block per slot).  A refinement references one site
+    // (tile_slot); sites are shared by every tile whose point satisfies the
+    // rebuild rule for them and are built NBLD at a time in the Fb/PN staging
+    // blocks.
+    DBuf<zd> CtC, PN, Fb, Finv, Dinv, T1p, pvec, d_zdag, zgemm_ws;
+    int NS = 0, NBLD = 0;
+    std::vector<zd> slot_z;
+    std::vector<double> slot_gam;
+    std::vector<int> slot_ref;
+    std::vector<int64_t> slot_last;
+    std::vector<char> slot_valid;
+    std::vector<char> slot_priv;     // built for one refinement (shifted or escalated): never shared
+    int64_t slot_clock = 0;
+    DBuf<double> d_shift;
+    DBuf<int> d_notpd;
+    HBuf<double> h_shift;
+    HBuf<int> h_notpd;
+    std::vector<int> tile_slot;      // per tile: site of the running refinement (-1: K = I)
     std::vector<char> usek;          // per tile: this refinement uses the base preconditioner
-    DBuf<int> d_listK, d_listI;
+    DBuf<int> d_listK, d_listI, d_gmap;
+    HBuf<int> h_gmap;
     bool use_prec = false;
-    void build_precond(const std::vector<int>& L);
-    void precond_apply(const int* dl, int nt, const zd* W, int64_t ws, zd* Y, int64_t ys);
+    void reset_slots();
+    // builds one site per entry of `sites` into free slots; slot ids out (-1:
+    // no free slot).  mu (optional): per-site shift, the factored matrix is
+    // N(z) - mu I (+ delta I when mu = 0); pd (optional) receives whether the
+    // Cholesky met only positive pivots; priv: sites are private to one tile.
+    std::vector<int> build_precond(const std::vector<zd>& sites, const std::vector<double>* mu = nullptr,
+                                   std::vector<char>* pd = nullptr, bool priv = false);
+    // slot whose site satisfies the rebuild rule at z with the smallest gamma |z - z_dag|, or -1
+    int find_slot(zd z) const;
+    void precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, zd* Y, int64_t ys);
     void zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, const zd* A, int64_t lda, int64_t sA,
                int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
-               double beta, int upper = 0, int tri = 0);
+               double beta, int upper = 0, int tri = 0, const int* gmap = nullptr, int cw = 0);
 
     KProf prof;
     ps_stats stats{};
@@ -197,6 +220,9 @@ struct Engine {
     // iteration for every listed tile (tiles may be at different iterations).
     std::vector<int> lob_it;          // per tile: iteration count (0 = after start)
     std::vector<double> lob_sigma;    // per tile: smallest Ritz value at exit
+    std::vector<double> lob_xi;       // per tile: smallest Ritz value after the last step
+    std::vector<int> esc_at;          // per tile: iteration of the next escalation
+    std::vector<char> site_exact;     // per tile: its preconditioner was built at its own point
     std::vector<zd> h_zt;             // per tile: current grid point
     DBuf<int> d_cdimt, d_pcols;       // per tile: width of S, width of P
     void lob_start(const std::vector<int>& L, uint64_t seed);

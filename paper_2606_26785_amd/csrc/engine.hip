@@ -486,6 +486,9 @@ void Engine::size_for(int tiles)
     d_cdimt.alloc(t); d_pcols.alloc(t);
     lob_it.assign(t, 0);
     lob_sigma.assign(t, 0.0);
+    lob_xi.assign(t, 0.0);
+    esc_at.assign(t, 0);
+    site_exact.assign(t, 0);
     h_zt.assign(t, zmake(0.0, 0.0)); d_list2.alloc(t); d_jobsrc.alloc(t);
     d_z.alloc(t);
     const size_t J = t * B;
@@ -501,19 +504,33 @@ void Engine::size_for(int tiles)
         for (size_t i = 0; i < t; ++i) { cv[i] = r; cv[t + i] = 2 * r; cv[2 * t + i] = 3 * r; }
         HIPCHK(hipMemcpy(cdim.p, cv.data(), sizeof(int) * 3 * t, hipMemcpyHostToDevice));
     }
+    NBLD = 0;
+    NS = 0;
     if (use_prec) {
         const size_t nn = (size_t)n * n;
-        PN.alloc(t * nn); Finv.alloc(t * nn); FinvH.alloc(t * nn);
-        Dinv.alloc(t * n * PRE_NB); T1p.alloc(t * n * PRE_NB); pvec.alloc(t * 2 * n); d_zdag.alloc(t);
+        // staging for up to 8 simultaneous constructions; the site pool holds
+        // one slot per tile plus the staging count (so a free slot always
+        // exists), within 96 GB
+        NBLD = 8;
+        const size_t cap = std::max<size_t>(2, ((size_t)96 << 30) / (nn * sizeof(zd)));
+        NS = (int)std::min<size_t>(t + NBLD, cap);
+        PN.alloc(NBLD * nn); Fb.alloc(NBLD * nn); Finv.alloc((size_t)NS * nn);
+        Dinv.alloc(NBLD * n * PRE_NB); T1p.alloc(NBLD * n * PRE_NB); pvec.alloc(NBLD * 2 * n); d_zdag.alloc(NBLD);
+        d_shift.alloc(NBLD); d_notpd.alloc(NBLD);
         zgemm_ws.alloc(std::max<size_t>((size_t)32 << 20, t * (size_t)n * r * 16));
     }
+    nrm2.alloc(std::max<size_t>(t, NBLD) * 3 * r);
+    slot_z.assign(NS, zmake(0.0, 0.0));
+    slot_gam.assign(NS, 0.0);
+    slot_ref.assign(NS, 0);
+    slot_last.assign(NS, 0);
+    slot_valid.assign(NS, 0);
+    slot_priv.assign(NS, 0);
+    tile_slot.assign(t, -1);
     d_listK.alloc(t); d_listI.alloc(t);
     usek.assign(t, 1);
-    zdag.assign(t, zmake(0.0, 0.0));
-    gam.assign(t, 0.0);
-    has_prec.assign(t, 0);
-    h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r)); h_nrm2.alloc(t * 3 * r);
-    h_small.alloc(t * 4 + 8); h_C.alloc(t * K * r + 8); h_list.alloc(t + 1); h_z.alloc(t + J);
+    h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r)); h_nrm2.alloc(std::max<size_t>(t, NBLD) * 3 * r);
+    h_small.alloc(std::max<size_t>(t, NBLD) * 4 + 8); h_C.alloc(t * K * r + 8); h_list.alloc(t + 1); h_z.alloc(t + J);
 }
 
 // ---------------------------------------------------------------------------

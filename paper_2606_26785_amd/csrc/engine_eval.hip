@@ -207,13 +207,13 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     const int b = std::max(1, P.batch);
     B = b;
     int ty = P.tiles_y > 0 ? P.tiles_y : (ny + b - 1) / b;
-    int tx = P.tiles_x > 0 ? P.tiles_x : std::max(1, (int)std::lround(nx / 50.0));
+    int tx = P.tiles_x > 0 ? P.tiles_x : std::max(1, (int)std::lround(nx / 20.0));
     ty = std::min(ty, ny);
     tx = std::min(tx, nx);
     tile_orders(nx, ny, tx, ty, b, tiles);
     size_for((int)tiles.size());
     for (auto& t : tiles) { t.cursor = 0; t.k = 0; }
-    std::fill(has_prec.begin(), has_prec.end(), 0);
+    reset_slots();
     upload_k();
     std::vector<uint8_t> fl(npts, 0);
     std::vector<double> sig(npts, 0.0);
@@ -229,9 +229,15 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     };
     // tile states: 0 idle (next point needs its Ritz test), 1 in LOBPCG, 2 done
     std::vector<int> state(T, 0);
-    for (int t = 0; t < T; ++t) if (tiles[t].done()) state[t] = 2;
     uint64_t step_seed = P.seed ^ 0x9e3779b97f4a7c15ull;
     int64_t loops = 0;
+    const double EPSM_E = 2.220446049250313e-16;
+    const double tau_c = P.tol_abs * nC;          // certification half-width
+    bool redo_pass = false;                       // Lipschitz re-refinement: no store updates
+    auto run_tiles = [&]() {
+    for (int t = 0; t < T; ++t) state[t] = tiles[t].done() ? 2 : 0;
+    std::fill(esc_at.begin(), esc_at.end(), P.esc_iters);
+    std::fill(site_exact.begin(), site_exact.end(), 0);
     while (true) {
         ++loops;
         // ---- A. idle tiles: Ritz test on their next window of points
@@ -241,7 +247,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         auto t0 = now();
         if (!idle.empty()) {
             stats.rounds++;
-            if (P.recycle) {
+            if (P.recycle && !redo_pass) {
                 std::vector<int> jt, jp;
                 for (int t : idle) {
                     if (tiles[t].k == 0) continue;
@@ -352,39 +358,80 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
                 launch_randfill(d_list.p, (int)Rr.size(), S.p, sS, n, n, r, nullptr, step_seed, st);
             }
-            // base preconditioner: build at the first refined point of a tile
-            // and rebuild at z when the Weyl-type bound of eq. (tauRecycle)
-            // fails; near-singular points (recycled Ritz value below
-            // rho_small ||M(z)||) have a well separated smallest singular
-            // value and run with K = I.  Without the coarse (two-level)
-            // correction nothing lifts the small end of the pencil spectrum,
-            // bounded below by (1 - gamma |z - z_dag|)^2, so the rule is applied
-            // to the condition-number bound ((1 + g)/(1 - g))^2 <= tau_max.
+            // base preconditioner.  Near-singular points (recycled Ritz value
+            // below rho_small ||M(z)||) have a well separated smallest
+            // singular value and run with K = I.  Every other refinement takes
+            // the site that satisfies the rebuild rule of eq. (tauRecycle) at z
+            // (base part only: without the coarse two-level correction nothing
+            // lifts the small end of the pencil spectrum, bounded below by
+            // (1 - gamma |z - z_dag|)^2, so the rule bounds the condition
+            // number ((1 + g)/(1 - g))^2 <= tau_max); when no site does, a new
+            // one is built at z.  Sites are shared by all tiles.
             if (use_prec) {
-                std::vector<int> Rb;
+                std::vector<int> pend;
+                std::vector<double> est(T, 0.0);
                 for (size_t i = 0; i < R.size(); ++i) {
                     const int t = R[i];
                     zd z = zs[tiles[t].order[tiles[t].cursor]];
                     usek[t] = 1;
+                    tile_slot[t] = -1;
+                    if (Rsrc[i] >= 0) est[t] = h_xi_keep[Rsrc[i]];
                     if (Rsrc[i] >= 0 && h_xi_keep[Rsrc[i]] <= P.rho_small * (nC + sqrt(zabs2(z)))) {
                         usek[t] = 0;
                         continue;
                     }
-                    bool rebuild = !has_prec[t];
-                    if (!rebuild) {
-                        double g = gam[t] * sqrt(zabs2(zsub(z, zdag[t])));
-                        if (g >= 1.0) rebuild = true;
-                        else rebuild = (1.0 + g) * (1.0 + g) / ((1.0 - g) * (1.0 - g)) > P.tau_max;
-                    }
-                    if (rebuild) {
-                        zdag[t] = z;
-                        Rb.push_back(t);
-                        fl[tiles[t].order[tiles[t].cursor]] |= PS_FLAG_REBUILD;
-                    }
+                    pend.push_back(t);
                 }
                 auto tp0 = now();
-                build_precond(Rb);
-                HIPCHK(hipStreamSynchronize(st));
+                while (!pend.empty()) {
+                    std::vector<int> rest;
+                    for (int t : pend) {
+                        int s = find_slot(zs[tiles[t].order[tiles[t].cursor]]);
+                        if (s >= 0) {
+                            tile_slot[t] = s;
+                            slot_ref[s]++;
+                            slot_last[s] = ++slot_clock;
+                        } else {
+                            rest.push_back(t);
+                        }
+                    }
+                    if (rest.empty()) break;
+                    // new sites: the first waiting point, and every later one
+                    // not within a quarter of a chosen site's recycled Ritz
+                    // value (an upper bound of sigma_min there, so such a point
+                    // is likely served by that site; find_slot decides)
+                    std::vector<zd> sites;
+                    std::vector<double> sest;
+                    for (int t : rest) {
+                        if ((int)sites.size() >= NBLD) break;
+                        zd z = zs[tiles[t].order[tiles[t].cursor]];
+                        bool near = false;
+                        for (size_t q = 0; q < sites.size() && !near; ++q)
+                            near = sest[q] > 0.0 && sqrt(zabs2(zsub(z, sites[q]))) <= 0.25 * sest[q];
+                        if (near) continue;
+                        sites.push_back(z);
+                        sest.push_back(est[t]);
+                        fl[tiles[t].order[tiles[t].cursor]] |= PS_FLAG_REBUILD;
+                    }
+                    std::vector<int> got = build_precond(sites);
+                    bool failed = sites.empty();
+                    for (int s : got) failed |= (s < 0);
+                    if (failed) {
+                        // pool exhausted (every slot referenced): nearest site
+                        // regardless of the rule, else K = I
+                        for (int t : rest) {
+                            zd z = zs[tiles[t].order[tiles[t].cursor]];
+                            int best = -1;
+                            for (int s = 0; s < NS; ++s)
+                                if (slot_valid[s] && (best < 0 || zabs2(zsub(z, slot_z[s])) < zabs2(zsub(z, slot_z[best]))))
+                                    best = s;
+                            if (best >= 0) { tile_slot[t] = best; slot_ref[best]++; }
+                            else usek[t] = 0;
+                        }
+                        break;
+                    }
+                    pend.swap(rest);
+                }
                 stats.t_precond_ms += ms(tp0, now());
             }
             h_z.alloc((size_t)T + 8);
@@ -393,7 +440,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             HIPCHK(hipMemcpyAsync(d_z.p, h_z.p, sizeof(zd) * T, hipMemcpyHostToDevice, st));
             step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
             lob_start(R, step_seed);
-            for (int t : R) state[t] = 1;
+            for (int t : R) { state[t] = 1; esc_at[t] = P.esc_iters; site_exact[t] = 0; }
         }
         // ---- C. one LOBPCG iteration for every running tile
         std::vector<int> run;
@@ -408,20 +455,88 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         std::vector<int> fin, okv;
         step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
         lob_step(run, step_seed, fin, okv);
+        // ---- C'. slow refinements (every esc_iters iterations without
+        // convergence).  A refinement whose smallest Ritz value xi is large
+        // enough for the test to resolve it gets two factorizations at its own
+        // point: N(z) - mu0 I with mu0 = (xi - tau)^2 + slack, whose
+        // positive definiteness (all Cholesky pivots positive) certifies
+        // sigma_min >= xi - tau by Sylvester's law of inertia, so xi is
+        // accepted; and N(z) - mu1 I with mu1 = (xi - 64 tau)^2, which, when
+        // positive definite, becomes the refinement's preconditioner: a shift
+        // just below the bottom of a cluster of singular values separates the
+        // cluster.  Smaller xi (the test cannot resolve it) get the exact site
+        // N(z) + delta I instead of a shared one.  slack bounds the rounding
+        // of forming N(z) and of the Cholesky factorization.
+        if (use_prec && P.esc_iters > 0) {
+            std::vector<char> isfin(T, 0);
+            for (int t : fin) isfin[t] = 1;
+            std::vector<zd> sites;
+            std::vector<double> mus;
+            std::vector<int> own, kind;
+            for (int t : run) {
+                if (isfin[t] || lob_it[t] < esc_at[t]) continue;
+                esc_at[t] = lob_it[t] + P.esc_iters;
+                const zd z = h_zt[t];
+                const double xi = lob_xi[t];
+                const double nz = nC + sqrt(zabs2(z));
+                const double slack = 8.0 * (double)n * EPSM_E * nz * nz;
+                if (tau_c > 0.0 && xi > 64.0 * tau_c && 2.0 * xi * tau_c - tau_c * tau_c > 4.0 * slack) {
+                    sites.push_back(z); mus.push_back((xi - tau_c) * (xi - tau_c) + slack); own.push_back(t);
+                    kind.push_back(0);
+                    sites.push_back(z); mus.push_back((xi - 64.0 * tau_c) * (xi - 64.0 * tau_c)); own.push_back(t);
+                    kind.push_back(1);
+                } else if (!site_exact[t]) {
+                    sites.push_back(z); mus.push_back(0.0); own.push_back(t); kind.push_back(2);
+                }
+            }
+            if (!sites.empty()) {
+                auto te0 = now();
+                std::vector<char> pd;
+                std::vector<int> got = build_precond(sites, &mus, &pd, true);
+                std::vector<char> certified(T, 0);
+                for (size_t i = 0; i < sites.size(); ++i)
+                    if (kind[i] == 0 && got[i] >= 0 && pd[i]) certified[own[i]] = 1;
+                for (size_t i = 0; i < sites.size(); ++i) {
+                    const int t = own[i], sl = got[i];
+                    if (sl < 0) continue;
+                    bool take = !certified[t] && ((kind[i] == 1 && pd[i]) || kind[i] == 2);
+                    if (take) {
+                        if (tile_slot[t] >= 0) slot_ref[tile_slot[t]]--;
+                        tile_slot[t] = sl;
+                        slot_ref[sl]++;
+                        usek[t] = 1;
+                        site_exact[t] = 1;
+                    } else {
+                        slot_valid[sl] = 0;       // certificate-only or indefinite factor
+                    }
+                }
+                for (int t = 0; t < T; ++t)
+                    if (certified[t]) {
+                        fin.push_back(t);
+                        okv.push_back(2);
+                        lob_sigma[t] = lob_xi[t];
+                        stats.certified++;
+                    }
+                stats.t_precond_ms += ms(te0, now());
+            }
+        }
         auto t3 = now();
         t_lob += ms(t1, t3) - 0.0 * ms(t1, t2);
         // ---- D. finished tiles: record sigma, update their recycled store
         for (size_t i = 0; i < fin.size(); ++i) {
             int t = fin[i];
+            if (use_prec && tile_slot[t] >= 0) { slot_ref[tile_slot[t]]--; tile_slot[t] = -1; }
             int pt = tiles[t].order[tiles[t].cursor];
             sig[pt] = lob_sigma[t];
             fl[pt] |= PS_FLAG_REFINED;
-            if (!okv[i]) { fl[pt] |= PS_FLAG_UNCERTIFIED; any_uncert = true; stats.uncertified++; }
+            if (okv[i] == 2) fl[pt] |= PS_FLAG_CERTIFIED;
+            if (!okv[i]) fl[pt] |= PS_FLAG_UNCERTIFIED;
+            else fl[pt] &= (uint8_t)~PS_FLAG_UNCERTIFIED;
             stats.refined++;
             tiles[t].cursor++;
         }
         if (!fin.empty()) {
-            if (P.recycle) update_store(fin);
+            if (P.recycle && !redo_pass) update_store(fin);
             for (int t : fin) state[t] = tiles[t].done() ? 2 : 0;
         }
         t_upd += ms(t3, now());
@@ -434,8 +549,63 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             fflush(stderr);
         }
     }
+    };
+    run_tiles();
+    // Lipschitz pass: sigma_min is 1-Lipschitz in z and every value computed
+    // here is a Ritz value, an upper bound of sigma_min, so a point with
+    // sigma(z) > sigma(z') + |z - z'| for one of its eight grid neighbours z'
+    // is certainly too high (a Ritz value that converged to a larger singular
+    // value).  Such points are refined again from a random start block, one
+    // point per tile, without touching any recycled store; repeated while
+    // violations remain (at most 4 passes).
+    if (P.lipschitz) {
+        auto zpt = [&](int64_t p) { return zs[p]; };
+        for (int pass = 0; pass < 4; ++pass) {
+            std::vector<int> viol;
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    const int64_t p = (int64_t)j * nx + i;
+                    bool v = false;
+                    for (int dj = -1; dj <= 1 && !v; ++dj)
+                        for (int di = -1; di <= 1 && !v; ++di) {
+                            if (!di && !dj) continue;
+                            const int ii = i + di, jj = j + dj;
+                            if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+                            const int64_t q = (int64_t)jj * nx + ii;
+                            const double d = sqrt(zabs2(zsub(zpt(p), zpt(q))));
+                            v = sig[p] > sig[q] + d * (1.0 + 1e-12) + 1e-13 * nC;
+                        }
+                    if (v) viol.push_back((int)p);
+                }
+            if (viol.empty()) break;
+            stats.lipschitz_redo += (int64_t)viol.size();
+            if (P.verbose) {
+                fprintf(stderr, "[ps] Lipschitz pass %d: %zu points refined again\n", pass, viol.size());
+                fflush(stderr);
+            }
+            for (size_t c0 = 0; c0 < viol.size(); c0 += (size_t)T) {
+                const size_t c1 = std::min(viol.size(), c0 + (size_t)T);
+                for (int t = 0; t < T; ++t) {
+                    tiles[t].order.clear();
+                    tiles[t].cursor = 0;
+                    tiles[t].k = 0;
+                }
+                for (size_t c = c0; c < c1; ++c) {
+                    tiles[c - c0].order.push_back(viol[c]);
+                    fl[viol[c]] = PS_FLAG_LIPSCHITZ;
+                }
+                upload_k();
+                redo_pass = true;
+                run_tiles();
+                redo_pass = false;
+            }
+        }
+    }
     if (prof.on) prof.collect(stats);
     stats.points = npts;
+    stats.uncertified = 0;
+    for (int64_t p = 0; p < npts; ++p) stats.uncertified += (fl[p] & PS_FLAG_UNCERTIFIED) ? 1 : 0;
+    any_uncert = stats.uncertified > 0;
     for (int64_t p = 0; p < npts; ++p) sigma[p] = sig[p];
     if (flags) memcpy(flags, fl.data(), npts);
     if (member)

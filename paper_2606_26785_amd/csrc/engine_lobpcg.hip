@@ -82,9 +82,8 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
     if (use_prec) {
         std::vector<int> Lk, Li;
         for (int t : L) (usek[t] ? Lk : Li).push_back(t);
-        upload_list(Lk, d_listK);
         upload_list(Li, d_listI);
-        precond_apply(d_listK.p, (int)Lk.size(), Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
+        precond_apply(Lk, Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
         launch_copy_cols(d_listI.p, (int)Li.size(), Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r,
                          st);
     } else {
@@ -151,6 +150,7 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
         return w0 <= std::max(P.eta_svd * nz * x0, floor_c * nz * nz * EPSM_L) || x0 <= P.eta_abs * nC;
     };
     std::vector<int> cand;
+    for (int t : L) lob_xi[t] = h_xi[(size_t)t * r3];
     for (int t : L) if (passes(t)) cand.push_back(t);
     std::vector<char> fin(T, 0);
     if (!cand.empty()) {

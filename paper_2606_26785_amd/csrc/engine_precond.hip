@@ -8,7 +8,7 @@
 
 void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, const zd* A, int64_t lda, int64_t sA,
                    int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
-                   double beta, int upper, int tri)
+                   double beta, int upper, int tri, const int* gmap, int cw)
 {
     if (nt <= 0 || M <= 0 || N <= 0) return;
     ZgemmArgs a;
@@ -31,6 +31,12 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
     a.beta = beta;
     a.upper = upper;
     a.tri = tri;
+    if (gmap) {
+        a.goff = gmap;
+        a.gcnt = gmap + nt;
+        a.gtile = gmap + 2 * nt;
+        a.cw = cw;
+    }
     // split K when the output is too small to fill the GPU (narrow right-hand sides)
     {
         int64_t wgs = ((M + 63) / 64) * ((N + 31) / 32) * nt;
@@ -51,80 +57,177 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
     prof.end(st, pi);
 }
 
-// K^{-1} W for the tiles in dl: Y = F^{-1} (F^{-*} W), W and Y n x r per tile
-void Engine::precond_apply(const int* dl, int nt, const zd* W, int64_t ws, zd* Y, int64_t ys)
+void Engine::reset_slots()
 {
-    if (nt <= 0) return;
-    const int64_t nn = n * n;
-    stats.sv_F += (int64_t)2 * nt * r;
-    zgemm(dl, nt, n, r, n, FinvH.p, n, nn, 0, W, n, ws, Tn2.p, n, (int64_t)n * r, 1.0, 0.0, 0, 2);
-    zgemm(dl, nt, n, r, n, Finv.p, n, nn, 0, Tn2.p, n, (int64_t)n * r, Y, n, ys, 1.0, 0.0, 0, 1);
+    std::fill(slot_valid.begin(), slot_valid.end(), 0);
+    std::fill(slot_ref.begin(), slot_ref.end(), 0);
+    std::fill(slot_last.begin(), slot_last.end(), 0);
+    std::fill(slot_priv.begin(), slot_priv.end(), 0);
+    std::fill(tile_slot.begin(), tile_slot.end(), -1);
+    slot_clock = 0;
 }
 
-// Build K = F^* F with F^* F = N(z_dag) + delta I for every tile in L, at the
-// z_dag already stored in zdag[] (right-looking blocked Cholesky, block
-// PRE_NB, trailing updates and the columns of F^{-1} on the matrix cores),
-// then gamma = ||F^{-1}||_2 by power iteration on F^{-1} F^{-*}.
-void Engine::build_precond(const std::vector<int>& L)
+// The rebuild rule of eq. (tauRecycle) for the base preconditioner alone:
+// with gamma = ||F^{-1}||_2, g = gamma |z - z_dag| bounds the drift of the
+// preconditioned spectrum, which stays within [(1 - g)^2, (1 + g)^2]; a site
+// serves z while g < 1 and ((1 + g) / (1 - g))^2 <= tau_max.
+int Engine::find_slot(zd z) const
+{
+    int best = -1;
+    double bg = 0.0;
+    for (int s = 0; s < NS; ++s) {
+        if (!slot_valid[s] || slot_priv[s]) continue;
+        const double d = sqrt(zabs2(zsub(z, slot_z[s])));
+        const double g = (d == 0.0) ? 0.0 : slot_gam[s] * d;   // a site always serves its own point
+        if (!(g < 1.0)) continue;
+        double q = (1.0 + g) / (1.0 - g);
+        if (q * q > P.tau_max) continue;
+        if (best < 0 || g < bg) { best = s; bg = g; }
+    }
+    return best;
+}
+
+// K^{-1} W = F^{-1} (F^{-*} W) for the tiles in L (each through its site):
+// tiles that share a site form one wide product, so each F^{-1} is streamed
+// once per 32 right-hand sides rather than once per tile.
+void Engine::precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, zd* Y, int64_t ys)
 {
     if (L.empty()) return;
-    const int nt = (int)L.size();
-    upload_list(L, d_list2);
-    const int* dl = d_list2.p;
+    std::vector<int> order(L);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tile_slot[x] < tile_slot[y]; });
+    std::vector<int> gs, goff, gcnt;
+    for (size_t i = 0; i < order.size(); ++i) {
+        int s = tile_slot[order[i]];
+        if (gs.empty() || gs.back() != s) { gs.push_back(s); goff.push_back((int)i); gcnt.push_back(0); }
+        gcnt.back()++;
+    }
+    const int ng = (int)gs.size();
+    const int nt = (int)order.size();
+    h_gmap.alloc((size_t)4 * ng + nt + 8);
+    d_gmap.alloc((size_t)4 * ng + nt + 8);
+    int* h = h_gmap.p;
+    int maxc = 0;
+    for (int g = 0; g < ng; ++g) {
+        h[g] = gs[g];                 // A index of group g (the slot)
+        h[ng + g] = goff[g];
+        h[2 * ng + g] = gcnt[g];
+        maxc = std::max(maxc, gcnt[g]);
+    }
+    for (int i = 0; i < nt; ++i) h[3 * ng + i] = order[i];
+    HIPCHK(hipMemcpyAsync(d_gmap.p, h, sizeof(int) * (3 * ng + nt), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     const int64_t nn = n * n;
-    h_z.alloc((size_t)T + 8);
-    for (int t = 0; t < T; ++t) h_z[t] = zdag[t];
-    HIPCHK(hipMemcpyAsync(d_zdag.p, h_z.p, sizeof(zd) * T, hipMemcpyHostToDevice, st));
-    double zmax = 0;
-    for (int t : L) zmax = std::max(zmax, sqrt(zabs2(zdag[t])));
-    const double scale = (op.normC + zmax) * (op.normC + zmax);
-    const double delta = 1e-13 * scale;
-    launch_form_normal(dl, nt, CtC.p, op.A.p, m, op.AH.p, n, d_zdag.p, delta, PN.p, nn, st);
-    launch_zero_tiles(dl, nt, Finv.p, nn, nn, st);
-    for (int64_t k0 = 0; k0 < n; k0 += PRE_NB) {
-        const int kb = (int)std::min<int64_t>(PRE_NB, n - k0);
-        launch_chol_diag(dl, nt, PN.p, nn, n, k0, kb, Dinv.p, (int64_t)n * PRE_NB, Finv.p, nn, 1e-2 * delta, st);
-        const int64_t k1 = k0 + kb, rest = n - k1;
-        if (rest > 0) {
-            // row panel: R[k, k1:] = R_kk^{-*} A[k, k1:]
-            zgemm(dl, nt, kb, rest, kb, Dinv.p + k0, n, (int64_t)n * PRE_NB, 1, PN.p + k0 + k1 * n, n, nn,
-                  PN.p + k0 + k1 * n, n, nn, 1.0, 0.0);
-            // trailing Hermitian update (upper part)
-            zgemm(dl, nt, rest, rest, kb, PN.p + k0 + k1 * n, n, nn, 1, PN.p + k0 + k1 * n, n, nn,
-                  PN.p + k1 + k1 * n, n, nn, -1.0, 1.0, 1);
+    stats.sv_F += (int64_t)2 * nt * r;
+    const int* gm = d_gmap.p + ng;
+    // T = F^{-*} W (F^{-*} lower triangular: A = Finv read conjugate-transposed)
+    zgemm(d_gmap.p, ng, n, (int64_t)maxc * r, n, Finv.p, n, nn, 1, W, n, ws, Tn2.p, n, (int64_t)n * r, 1.0, 0.0, 0,
+          2, gm, r);
+    // Y = F^{-1} T
+    zgemm(d_gmap.p, ng, n, (int64_t)maxc * r, n, Finv.p, n, nn, 0, Tn2.p, n, (int64_t)n * r, Y, n, ys, 1.0, 0.0, 0,
+          1, gm, r);
+}
+
+// Build one site per entry of `sites` (z_dag): N(z_dag) + delta I, its upper
+// Cholesky factor F by a right-looking blocked Cholesky (block PRE_NB,
+// trailing updates and the columns of F^{-1} on the matrix cores), F^{-1}
+// formed alongside, then gamma = ||F^{-1}||_2 by power iteration on
+// F^{-1} F^{-*}.  Up to NBLD sites are built at once in the staging blocks
+// and copied into free slots (least recently used first).
+std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::vector<double>* mu,
+                                       std::vector<char>* pd, bool priv)
+{
+    std::vector<int> out;
+    if (pd) pd->assign(sites.size(), 0);
+    const int64_t nn = n * n;
+    for (size_t b0 = 0; b0 < sites.size(); b0 += (size_t)NBLD) {
+        const int nb = (int)std::min<size_t>((size_t)NBLD, sites.size() - b0);
+        std::vector<int> pos(nb);
+        for (int i = 0; i < nb; ++i) pos[i] = i;
+        upload_list(pos, d_list2);
+        const int* dl = d_list2.p;
+        h_z.alloc((size_t)nb + 8);
+        double zmax = 0;
+        for (int i = 0; i < nb; ++i) {
+            h_z[i] = sites[b0 + i];
+            zmax = std::max(zmax, sqrt(zabs2(sites[b0 + i])));
         }
-        if (k0 > 0) {
-            // F^{-1}[0:k0, k-block] = -F^{-1}[0:k0, 0:k0] R[0:k0, k-block] R_kk^{-1}
-            zgemm(dl, nt, k0, kb, k0, Finv.p, n, nn, 0, PN.p + k0 * n, n, nn, T1p.p, n, (int64_t)n * PRE_NB, 1.0,
-                  0.0);
-            zgemm(dl, nt, k0, kb, kb, T1p.p, n, (int64_t)n * PRE_NB, 0, Dinv.p + k0, n, (int64_t)n * PRE_NB,
-                  Finv.p + k0 * n, n, nn, -1.0, 0.0);
+        HIPCHK(hipMemcpyAsync(d_zdag.p, h_z.p, sizeof(zd) * nb, hipMemcpyHostToDevice, st));
+        const double scale = (op.normC + zmax) * (op.normC + zmax);
+        const double delta = 1e-13 * scale;
+        h_shift.alloc((size_t)nb + 8);
+        for (int i = 0; i < nb; ++i) {
+            double mv = mu ? (*mu)[b0 + i] : 0.0;
+            h_shift[i] = (mv == 0.0) ? delta : -mv;
         }
-    }
-    launch_conj_transpose_b(dl, nt, Finv.p, nn, n, FinvH.p, st);
-    HIPCHK(hipGetLastError());
-    // gamma^2 = lambda_max(F^{-1} F^{-*}) by power iteration
-    const int64_t sp = 2 * n;
-    launch_randfill(dl, nt, pvec.p, sp, n, n, 1, nullptr, 0x7a11ull, st);
-    std::vector<double> g2(T, 0.0);
-    for (int it = 0; it < 30; ++it) {
-        zgemm(dl, nt, n, 1, n, FinvH.p, n, nn, 0, pvec.p, n, sp, pvec.p + n, n, sp, 1.0, 0.0);
-        zgemm(dl, nt, n, 1, n, Finv.p, n, nn, 0, pvec.p + n, n, sp, pvec.p, n, sp, 1.0, 0.0);
-        BlockList Lp = bl_empty(n);
-        bl_add(Lp, pvec.p, sp, n, 1, nullptr, 0);
-        colnorm2(dl, nt, Lp, 1, nrm2.p, 3 * r);
-        if (it == 29 || it % 10 == 9) {
-            HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * 3 * r, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            for (int t : L) g2[t] = sqrt(h_nrm2[(size_t)t * 3 * r]);
+        HIPCHK(hipMemcpyAsync(d_shift.p, h_shift.p, sizeof(double) * nb, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(d_notpd.p, 0, sizeof(int) * nb, st));
+        launch_form_normal(dl, nb, CtC.p, op.A.p, m, op.AH.p, n, d_zdag.p, d_shift.p, PN.p, nn, st);
+        launch_zero_tiles(dl, nb, Fb.p, nn, nn, st);
+        for (int64_t k0 = 0; k0 < n; k0 += PRE_NB) {
+            const int kb = (int)std::min<int64_t>(PRE_NB, n - k0);
+            launch_chol_diag(dl, nb, PN.p, nn, n, k0, kb, Dinv.p, (int64_t)n * PRE_NB, Fb.p, nn, 1e-2 * delta,
+                             d_notpd.p, st);
+            const int64_t k1 = k0 + kb, rest = n - k1;
+            if (rest > 0) {
+                // row panel: R[k, k1:] = R_kk^{-*} A[k, k1:]
+                zgemm(dl, nb, kb, rest, kb, Dinv.p + k0, n, (int64_t)n * PRE_NB, 1, PN.p + k0 + k1 * n, n, nn,
+                      PN.p + k0 + k1 * n, n, nn, 1.0, 0.0);
+                // trailing Hermitian update (upper part)
+                zgemm(dl, nb, rest, rest, kb, PN.p + k0 + k1 * n, n, nn, 1, PN.p + k0 + k1 * n, n, nn,
+                      PN.p + k1 + k1 * n, n, nn, -1.0, 1.0, 1);
+            }
+            if (k0 > 0) {
+                // F^{-1}[0:k0, k-block] = -F^{-1}[0:k0, 0:k0] R[0:k0, k-block] R_kk^{-1}
+                zgemm(dl, nb, k0, kb, k0, Fb.p, n, nn, 0, PN.p + k0 * n, n, nn, T1p.p, n, (int64_t)n * PRE_NB, 1.0,
+                      0.0);
+                zgemm(dl, nb, k0, kb, kb, T1p.p, n, (int64_t)n * PRE_NB, 0, Dinv.p + k0, n, (int64_t)n * PRE_NB,
+                      Fb.p + k0 * n, n, nn, -1.0, 0.0);
+            }
         }
-        dim3 g((unsigned)((n + 255) / 256), nt);
-        // normalise
-        launch_scale_cols(dl, nt, pvec.p, sp, n, n, 1, nrm2.p, 3 * r, 2, st);
+        HIPCHK(hipGetLastError());
+        // gamma^2 = lambda_max(F^{-1} F^{-*}) by power iteration
+        const int64_t sp = 2 * n;
+        launch_randfill(dl, nb, pvec.p, sp, n, n, 1, nullptr, 0x7a11ull, st);
+        std::vector<double> g2(nb, 0.0);
+        for (int it = 0; it < 30; ++it) {
+            zgemm(dl, nb, n, 1, n, Fb.p, n, nn, 1, pvec.p, n, sp, pvec.p + n, n, sp, 1.0, 0.0, 0, 2);
+            zgemm(dl, nb, n, 1, n, Fb.p, n, nn, 0, pvec.p + n, n, sp, pvec.p, n, sp, 1.0, 0.0, 0, 1);
+            BlockList Lp = bl_empty(n);
+            bl_add(Lp, pvec.p, sp, n, 1, nullptr, 0);
+            colnorm2(dl, nb, Lp, 1, nrm2.p, 3 * r);
+            if (it == 29) {
+                HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * nb * 3 * r, hipMemcpyDeviceToHost, st));
+                h_notpd.alloc((size_t)nb + 8);
+                HIPCHK(hipMemcpyAsync(h_notpd.p, d_notpd.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (int i = 0; i < nb; ++i) g2[i] = sqrt(h_nrm2[(size_t)i * 3 * r]);
+                if (pd)
+                    for (int i = 0; i < nb; ++i) (*pd)[b0 + i] = h_notpd[i] == 0;
+            }
+            launch_scale_cols(dl, nb, pvec.p, sp, n, n, 1, nrm2.p, 3 * r, 2, st);
+        }
+        for (int i = 0; i < nb; ++i) {
+            // slot: an unused one, else the least recently used unreferenced one
+            int s = -1;
+            for (int q = 0; q < NS && s < 0; ++q) if (!slot_valid[q]) s = q;
+            if (s < 0) {
+                for (int q = 0; q < NS; ++q) {
+                    if (slot_ref[q] > 0) continue;
+                    if (s < 0 || slot_last[q] < slot_last[s]) s = q;
+                }
+            }
+            out.push_back(s);
+            if (s < 0) continue;
+            HIPCHK(hipMemcpyAsync(Finv.p + (size_t)s * nn, Fb.p + (size_t)i * nn, sizeof(zd) * nn,
+                                  hipMemcpyDeviceToDevice, st));
+            slot_valid[s] = 1;
+            slot_priv[s] = priv ? 1 : 0;
+            slot_z[s] = sites[b0 + i];
+            slot_gam[s] = sqrt(std::max(g2[i], 0.0));
+            slot_last[s] = ++slot_clock;
+            stats.rebuilds++;
+        }
+        HIPCHK(hipStreamSynchronize(st));
     }
-    for (int t : L) {
-        gam[t] = sqrt(std::max(g2[t], 0.0));
-        has_prec[t] = 1;
-    }
-    stats.rebuilds += nt;
+    return out;
 }

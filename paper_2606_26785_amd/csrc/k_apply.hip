@@ -184,6 +184,9 @@ __global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
     const int bidx = blockIdx.z % nb, split = blockIdx.z / nb;
     const int tile = a.list ? a.list[bidx] : bidx;
     if (a.upper && i0 > j0 + BN - 1) return;
+    const int64_t Nb = a.gtile ? (int64_t)a.gcnt[bidx] * a.cw : a.N;
+    if (j0 >= Nb) return;
+    const int* gt = a.gtile ? a.gtile + a.goff[bidx] : nullptr;
     const int64_t kc = (a.K + a.splitk - 1) / a.splitk;
     int64_t kbeg = (int64_t)split * kc;
     int64_t kend = (kbeg + kc < a.K) ? kbeg + kc : a.K;
@@ -192,8 +195,19 @@ __global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
     if (a.tri == 1 && kbeg < i0) kbeg = (i0 / BK) * BK > kbeg ? (i0 / BK) * BK : kbeg;
     if (a.tri == 2 && kend > i0 + BM) kend = i0 + BM;
     const zd* A = a.A + (size_t)tile * a.strideA;
-    const zd* B = a.B + (size_t)tile * a.strideB;
-    zd* C = a.C + (size_t)tile * a.strideC;
+    const zd* B = a.B + (size_t)(gt ? 0 : tile) * a.strideB;
+    zd* C = a.C + (size_t)(gt ? 0 : tile) * a.strideC;
+    // B staging: thread tid loads rows k0 + tid % BK of columns
+    // j0 + tid / BK + (NT / BK) q, q = 0 .. BN*BK/NT - 1; their base pointers
+    // (column-map mode: through the tile map) are fixed for the whole K loop
+    constexpr int BQ = BN * BK / NT;
+    const zd* bcol[BQ];
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+        int64_t gj = j0 + tid / BK + (NT / BK) * q;
+        bcol[q] = nullptr;
+        if (gj < Nb) bcol[q] = gt ? B + (size_t)gt[gj / a.cw] * a.strideB + (gj % a.cw) * a.ldb : B + gj * a.ldb;
+    }
     dvec4 acc_re[2], acc_im[2];
     for (int c = 0; c < 2; ++c) {
         acc_re[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
@@ -214,10 +228,11 @@ __global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
                 As[kk][ii] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
             }
         }
-        for (int e = tid; e < BN * BK; e += NT) {
-            int kk = e % BK, jj = e / BK;
-            int64_t gj = j0 + jj, gk = k0 + kk;
-            Bs[kk][jj] = (gj < a.N && gk < kend) ? B[gk + gj * a.ldb] : zmake(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int kk = tid % BK, jj = tid / BK + (NT / BK) * q;
+            const int64_t gk = k0 + kk;
+            Bs[kk][jj] = (bcol[q] && gk < kend) ? bcol[q][gk] : zmake(0.0, 0.0);
         }
         __syncthreads();
 #pragma unroll
@@ -238,7 +253,8 @@ __global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         int64_t col = j0 + cb * 16 + (lane & 15);
-        if (col >= a.N) continue;
+        if (col >= Nb) continue;
+        zd* ccol = gt ? C + (size_t)gt[col / a.cw] * a.strideC + (col % a.cw) * a.ldc : C + col * a.ldc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             int64_t row = i0 + wave * 16 + (lane >> 4) + 4 * v;
@@ -249,7 +265,7 @@ __global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
                 continue;
             }
             zd val = zmake(a.alpha * acc_re[cb][v], a.alpha * acc_im[cb][v]);
-            zd* cp = C + row + col * a.ldc;
+            zd* cp = ccol + row;
             if (a.beta != 0.0) val = zadd(val, *cp);
             *cp = val;
         }
@@ -264,9 +280,16 @@ __global__ void __launch_bounds__(NT) k_zgemm_reduce(ZgemmArgs a, int nb)
     int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (e >= a.M * a.N) return;
     int64_t row = e % a.M, col = e / a.M;
+    zd* cp;
+    if (a.gtile) {
+        if (col >= (int64_t)a.gcnt[bidx] * a.cw) return;
+        const int ct = a.gtile[a.goff[bidx] + col / a.cw];
+        cp = a.C + (size_t)ct * a.strideC + row + (col % a.cw) * a.ldc;
+    } else {
+        cp = a.C + (size_t)tile * a.strideC + row + col * a.ldc;
+    }
     zd s = zmake(0.0, 0.0);
     for (int sp = 0; sp < a.splitk; ++sp) s = zadd(s, a.ws[((size_t)sp * nb + bidx) * a.M * a.N + e]);
-    zd* cp = a.C + (size_t)tile * a.strideC + row + col * a.ldc;
     zd val = zscale(s, a.alpha);
     if (a.beta != 0.0) val = zadd(val, *cp);
     *cp = val;

@@ -9,9 +9,9 @@
 
 #define NT 256
 
-// N = C^*C - conj(z) S^*C - z C^*S + (|z|^2 + delta) I for each tile in list
+// N = C^*C - conj(z) S^*C - z C^*S + (|z|^2 + shift) I for each tile in list
 __global__ void k_form_normal(const int* list, const zd* CtC, const zd* C, int64_t ldc, const zd* CH, int64_t n,
-                              const zd* zdag, double delta, zd* N, int64_t strideN)
+                              const zd* zdag, const double* shift, zd* N, int64_t strideN)
 {
     const int tile = list[blockIdx.y];
     int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -23,26 +23,27 @@ __global__ void k_form_normal(const int* list, const zd* CtC, const zd* C, int64
     zd ch = CH[i + j * n];      // C^* S: first n columns of C^*
     v = zsub(v, zmul(zconj(z), c));
     v = zsub(v, zmul(z, ch));
-    if (i == j) v.x += zabs2(z) + delta;
+    if (i == j) v.x += zabs2(z) + shift[tile];
     N[(size_t)tile * strideN + i + j * n] = v;
 }
 
 void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int64_t ldc, const zd* CH,
-                        int64_t n, const zd* zdag, double delta, zd* N, int64_t strideN, hipStream_t s)
+                        int64_t n, const zd* zdag, const double* shift, zd* N, int64_t strideN, hipStream_t s)
 {
     if (nt <= 0) return;
     dim3 g((unsigned)((n * n + NT - 1) / NT), nt);
-    hipLaunchKernelGGL(k_form_normal, g, dim3(NT), 0, s, list, CtC, C, ldc, CH, n, zdag, delta, N, strideN);
+    hipLaunchKernelGGL(k_form_normal, g, dim3(NT), 0, s, list, CtC, C, ldc, CH, n, zdag, shift, N, strideN);
 }
 
 // Diagonal block (kb <= 32) of the blocked Cholesky: R_kk with R_kk^* R_kk = A_kk
 // (upper triangle of A_kk read), written back into A; its inverse written to
 // Dinv (rows k0.., ld n) and to the diagonal block of Finv (zeros below the
-// diagonal).  Pivots are floored at `floor_piv` (the matrix is N + delta I,
-// positive definite in exact arithmetic).
+// diagonal).  A pivot that is not positive sets notpd[tile] (the matrix is not
+// numerically positive definite); pivots are then floored at `floor_piv` so
+// that the factor stays finite.
 __global__ void __launch_bounds__(NT) k_chol_diag(const int* list, zd* A, int64_t strideA, int64_t n, int64_t k0,
                                                   int kb, zd* Dinv, int64_t strideD, zd* Finv, int64_t strideF,
-                                                  double floor_piv)
+                                                  double floor_piv, int* notpd)
 {
     __shared__ zd R[32][33];
     __shared__ zd X[32][33];
@@ -58,6 +59,7 @@ __global__ void __launch_bounds__(NT) k_chol_diag(const int* list, zd* A, int64_
     for (int j = 0; j < kb; ++j) {
         if (tid == 0) {
             double d = R[j][j].x;
+            if (!(d > 0.0)) notpd[tile] = 1;
             if (!(d > floor_piv)) d = floor_piv;
             piv = sqrt(d);
         }
@@ -95,11 +97,11 @@ __global__ void __launch_bounds__(NT) k_chol_diag(const int* list, zd* A, int64_
 }
 
 void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
-                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, hipStream_t s)
+                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s)
 {
     if (nt <= 0) return;
     hipLaunchKernelGGL(k_chol_diag, dim3(nt), dim3(NT), 0, s, list, A, strideA, n, k0, kb, Dinv, strideD, Finv,
-                       strideF, floor_piv);
+                       strideF, floor_piv, notpd);
 }
 
 // batched conjugate transpose of square n x n matrices (per tile)

@@ -180,14 +180,19 @@ struct ZgemmArgs {
     int tri;                         // 1: A upper triangular, 2: A lower triangular (skip zero blocks)
     int splitk;                      // > 1: K split over workgroups, partials in ws
     zd* ws;                          // splitk * nbatch * M * N partial products
+    // column-map mode (gtile != NULL): batch entry b multiplies A[list[b]] by
+    // the column blocks of the gcnt[b] tiles gtile[goff[b] ...] (cw columns
+    // each, B + tile * strideB, C + tile * strideC), so tiles that share an A
+    // are one wide product; N is the largest gcnt[b] * cw
+    const int* gtile; const int* goff; const int* gcnt; int cw;
 };
 void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s);
 
 // dense base preconditioner (k_precond.hip)
 #define PRE_NB 32
 void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int64_t ldc, const zd* CH,
-                        int64_t n, const zd* zdag, double delta, zd* N, int64_t strideN, hipStream_t s);
+                        int64_t n, const zd* zdag, const double* shift, zd* N, int64_t strideN, hipStream_t s);
 void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
-                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, hipStream_t s);
+                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s);
 void launch_conj_transpose_b(const int* list, int nt, const zd* A, int64_t stride, int64_t n, zd* B, hipStream_t s);
 void launch_zero_tiles(const int* list, int nt, zd* A, int64_t stride, int64_t count, hipStream_t s);

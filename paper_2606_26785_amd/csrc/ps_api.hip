@@ -45,6 +45,11 @@ void ps_default_params(ps_params* p)
     p->seed = 20261203ull;
     p->eta_abs = 1e-9;
     p->rho_small = 1e-5;
+    p->profile = 0;
+    p->verbose = 0;
+    p->tol_abs = 5e-9;
+    p->esc_iters = 30;
+    p->lipschitz = 1;
 }
 
 const char* ps_strerror(ps_status s)
@@ -84,7 +89,8 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
     if (p.kbar_max < p.rbar || p.kbar_max % p.rbar || p.kbar_max > 64)
         return fail(PS_EINVAL, "kbar_max must be a multiple of rbar, <= 64");
     if (p.max_iters < 1 || p.batch < 1) return fail(PS_EINVAL, "max_iters and batch must be positive");
-    if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0) || !(p.eta_abs >= 0) || p.eta_abs > 1e-8)
+    if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0) || !(p.eta_abs >= 0) || p.eta_abs > 1e-8 ||
+        !(p.tol_abs >= 0) || p.tol_abs > 1e-6 || p.esc_iters < 0)
         return fail(PS_EINVAL, "bad tolerances");
     if (p.precond > 1 || p.precond < -1) return fail(PS_EINVAL, "precond must be -1, 0 or 1");
     if (p.precond == 1 && d->kind != PS_DENSE)
@@ -195,7 +201,7 @@ extern "C" ps_status ps_debug_apply(ps_matrix* h, int32_t herm, double z_re, dou
 
 extern "C" double ps_debug_norm(const ps_matrix* h) { return h ? h->eng.op.normC : 0.0; }
 
-// Build the dense base preconditioner of slot 0 at z and copy F^{-1} (n x n,
+// Build one dense base-preconditioner site at z and copy F^{-1} (n x n,
 // column-major) to the host; returns gamma = ||F^{-1}||_2 estimate.
 extern "C" ps_status ps_debug_precond(ps_matrix* h, double z_re, double z_im, double* Finv_out, double* gamma_out)
 {
@@ -203,13 +209,14 @@ extern "C" ps_status ps_debug_precond(ps_matrix* h, double z_re, double z_im, do
     try {
         Engine& E = h->eng;
         if (!E.use_prec) return fail(PS_EUNSUPPORTED, "no dense preconditioner on this handle");
-        if (E.T < 1 || E.zdag.empty()) E.size_for(std::max(E.T, 1));
-        E.zdag[0] = zmake(z_re, z_im);
-        std::vector<int> L = {0};
-        E.build_precond(L);
+        if (E.T < 1 || E.NS < 1) E.size_for(std::max(E.T, 1));
+        E.reset_slots();
+        std::vector<int> sl = E.build_precond({zmake(z_re, z_im)});
+        if (sl.empty() || sl[0] < 0) return fail(PS_ENOMEM, "no preconditioner slot");
         HIPCHK(hipStreamSynchronize(E.st));
-        HIPCHK(hipMemcpy(Finv_out, E.Finv.p, sizeof(zd) * E.n * E.n, hipMemcpyDeviceToHost));
-        if (gamma_out) *gamma_out = E.gam[0];
+        HIPCHK(hipMemcpy(Finv_out, E.Finv.p + (size_t)sl[0] * E.n * E.n, sizeof(zd) * E.n * E.n,
+                         hipMemcpyDeviceToHost));
+        if (gamma_out) *gamma_out = E.slot_gam[sl[0]];
         return PS_OK;
     } catch (const std::exception& e) {
         return fail(PS_EDEVICE, e.what());

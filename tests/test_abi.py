@@ -1,0 +1,76 @@
+"""The C-ABI library: it loads without a GPU, exports every function the
+headers declare, and the Python binding's structures follow the header's
+field order (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INC = os.path.join(ROOT, "include")
+
+
+def _headers():
+    return [os.path.join(INC, f) for f in sorted(os.listdir(INC)) if f.endswith(".h")]
+
+
+def _declared_functions():
+    names = set()
+    for h in _headers():
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w\s\*]*?\b(ps_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def _struct_fields(name):
+    src = open(os.path.join(INC, "ps.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    end = re.search(r"\}\s*" + name + ";", src)
+    assert end, name
+    start = src.rfind("typedef struct {", 0, end.start())
+    body = src[start + len("typedef struct {"):end.start()]
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        decl = re.sub(r"\[\d+\]", "", decl)
+        for part in decl.split(","):
+            fields.append(re.findall(r"\w+", part)[-1])
+    return fields
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2606_26785_amd import build
+    path = build.OUT
+    if not os.path.exists(path):
+        pytest.skip("libps.so not built (run __graft_entry__.build())")
+    return ctypes.CDLL(path)
+
+
+def test_headers_declare_the_boundary():
+    names = _declared_functions()
+    for need in ("ps_create", "ps_grid", "ps_eval", "ps_destroy", "ps_grid_destroy", "ps_default_params",
+                 "ps_strerror", "ps_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_structs_follow_header():
+    import paper_2606_26785_amd as P
+    for cname, cls in (("ps_params", P.ps_params), ("ps_stats", P.ps_stats), ("ps_matrix_desc", P.ps_matrix_desc)):
+        assert [f[0] for f in cls._fields_] == _struct_fields(cname), cname
+
+
+def test_default_params_without_gpu(lib):
+    import paper_2606_26785_amd as P
+    p = P.default_params()
+    assert p.r == 8 and p.k_max == 32 and p.eta > 0 and p.lipschitz == 1
