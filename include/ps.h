@@ -111,7 +111,7 @@ typedef struct {
                            kernels with HIP events (fills the k_* stats) */
     int32_t verbose;    /* 1: progress lines on stderr */
     double tol_abs;     /* certification half-width tau as a fraction of
-                           ||C||_2 (default 5e-9): a refinement still running
+                           ||C||_2 (default 8e-9): a refinement still running
                            after esc_iters iterations is accepted when
                            N(z) - mu I, mu = (xi - tau)^2 + rounding slack, is
                            positive definite (then xi - tau <= sigma_min <= xi);
@@ -121,10 +121,10 @@ typedef struct {
                            N(z) - (xi - 64 tau)^2 I, or an exact site at z
                            (default 30; 0 disables) */
     int32_t lipschitz;  /* 1 (default): after the sweep, points whose value
-                           exceeds a grid neighbour's by more than their
-                           distance (sigma_min is 1-Lipschitz, computed values
-                           are upper bounds) are refined again from a random
-                           start */
+                           exceeds an upper bound from a finished grid
+                           neighbour (the norm of C(z) on the neighbour's
+                           singular vector, or the 1-Lipschitz bound) are
+                           refined again from a random start */
 } ps_params;
 
 typedef struct {
@@ -142,7 +142,9 @@ typedef struct {
     int64_t sv_F;          /* column solves / applies with F^{-1}, F^{-*} */
     int64_t rounds;        /* scheduler rounds */
     int64_t certified;     /* refinements ended by the inertia test (tol_abs) */
-    int64_t lipschitz_redo;/* points refined again by the Lipschitz pass */
+    int64_t lipschitz_redo;/* points refined again by the neighbour pass */
+    int64_t guard_rejects; /* points that passed eq. (tolC) above a neighbour bound */
+    int64_t cert_tests;    /* inertia tests (Cholesky of N(z) - mu I) run */
     double t_total_ms;     /* wall time of ps_eval */
     double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
     /* with profile = 1: event-timed kernel classes (launches, device ms,
@@ -163,7 +165,7 @@ typedef struct {
 #define PS_FLAG_PROJ_REFINED 8u /* projection subspace refined here */
 #define PS_FLAG_REBUILD 16u     /* base preconditioner rebuilt here */
 #define PS_FLAG_CERTIFIED 32u   /* sigma certified by the inertia test */
-#define PS_FLAG_LIPSCHITZ 64u   /* refined again after a Lipschitz violation */
+#define PS_FLAG_LIPSCHITZ 64u   /* refined again after a neighbour-bound violation */
 
 void ps_default_params(ps_params* p);
 

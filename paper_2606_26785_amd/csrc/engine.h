@@ -117,6 +117,11 @@ struct Engine {
     // singular store (primary + update scratch)
     DBuf<zd> sV, sW1, sW3, sW4, uV, uW1, uW3, uW4;
     DBuf<zd> sRA, sRres;
+    DBuf<zd> sH;          // per tile: H = V^* S^* C V (k x k), first-order coefficients of Ritz vectors
+    DBuf<zd> j_gam, d_gamt;   // per Ritz job / per tile: gamma = (S x)^* C(z) x of the first Ritz vector
+    HBuf<zd> h_gamj, h_gamt;
+    std::vector<zd> pgam;     // per grid point: gamma of the vector behind sigma
+    std::vector<uint8_t> pgok;
     DBuf<zdd> gdd;        // Gram workspace (per tile, (4K)^2)
     DBuf<int> d_k, d_q, d_l;
 
@@ -154,7 +159,7 @@ struct Engine {
     // (tile_slot); sites are shared by every tile whose point satisfies the
     // rebuild rule for them and are built NBLD at a time in the Fb/PN staging
     // blocks.
-    DBuf<zd> CtC, PN, Fb, Finv, Dinv, T1p, pvec, d_zdag, zgemm_ws;
+    DBuf<zd> CtC, PN, Fb, Finv, Dinv, T1p, T2p, pvec, d_zdag, zgemm_ws;
     int NS = 0, NBLD = 0;
     std::vector<zd> slot_z;
     std::vector<double> slot_gam;
@@ -177,8 +182,9 @@ struct Engine {
     // no free slot).  mu (optional): per-site shift, the factored matrix is
     // N(z) - mu I (+ delta I when mu = 0); pd (optional) receives whether the
     // Cholesky met only positive pivots; priv: sites are private to one tile.
+    // cert_only: factor only (no F^{-1}, no slot), for the inertia test
     std::vector<int> build_precond(const std::vector<zd>& sites, const std::vector<double>* mu = nullptr,
-                                   std::vector<char>* pd = nullptr, bool priv = false);
+                                   std::vector<char>* pd = nullptr, bool priv = false, bool cert_only = false);
     // slot whose site satisfies the rebuild rule at z with the smallest gamma |z - z_dag|, or -1
     int find_slot(zd z) const;
     void precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, zd* Y, int64_t ys);
@@ -223,6 +229,8 @@ struct Engine {
     std::vector<double> lob_xi;       // per tile: smallest Ritz value after the last step
     std::vector<int> esc_at;          // per tile: iteration of the next escalation
     std::vector<char> site_exact;     // per tile: its preconditioner was built at its own point
+    std::vector<double> lob_prev;     // per tile: xi after the previous step
+    std::vector<int> stag, cert_next, cert_fail;   // per tile: inertia-test bookkeeping
     std::vector<zd> h_zt;             // per tile: current grid point
     DBuf<int> d_cdimt, d_pcols;       // per tile: width of S, width of P
     void lob_start(const std::vector<int>& L, uint64_t seed);

@@ -470,6 +470,9 @@ void Engine::size_for(int tiles)
     sV.alloc(t * nk); sW1.alloc(t * mk); sW3.alloc(t * nk); sW4.alloc(t * nk);
     uV.alloc(t * nk); uW1.alloc(t * mk); uW3.alloc(t * nk); uW4.alloc(t * nk);
     sRA.alloc(t * 4 * K * K);
+    sH.alloc(t * K * K);
+    d_gamt.alloc(t);
+    h_gamt.alloc(t + 8);
     sRres.alloc(t * 16 * K * K);
     const int cmax = std::max(4 * K, 3 * r);
     gdd.alloc(t * cmax * cmax);
@@ -489,11 +492,15 @@ void Engine::size_for(int tiles)
     lob_xi.assign(t, 0.0);
     esc_at.assign(t, 0);
     site_exact.assign(t, 0);
+    lob_prev.assign(t, 0.0);
+    stag.assign(t, 0);
+    cert_next.assign(t, 0);
+    cert_fail.assign(t, 0);
     h_zt.assign(t, zmake(0.0, 0.0)); d_list2.alloc(t); d_jobsrc.alloc(t);
     d_z.alloc(t);
     const size_t J = t * B;
     j_tile.alloc(J); j_z.alloc(J); j_G.alloc(J * K * r);
-    j_nrm.alloc(J); j_xi.alloc(J); j_res.alloc(J); j_acc.alloc(J);
+    j_nrm.alloc(J); j_xi.alloc(J); j_res.alloc(J); j_acc.alloc(J); j_gam.alloc(J); h_gamj.alloc(J + 8);
     gram_ws_bytes = std::max<size_t>((size_t)256 << 20, t * (size_t)cmax * cmax * sizeof(zdd) * 2);
     gram_ws.alloc(gram_ws_bytes);
     const size_t maxw = (size_t)std::max(r, P.rbar);
@@ -508,14 +515,14 @@ void Engine::size_for(int tiles)
     NS = 0;
     if (use_prec) {
         const size_t nn = (size_t)n * n;
-        // staging for up to 8 simultaneous constructions; the site pool holds
+        // staging for up to 16 simultaneous constructions; the site pool holds
         // one slot per tile plus the staging count (so a free slot always
         // exists), within 96 GB
-        NBLD = 8;
+        NBLD = 16;
         const size_t cap = std::max<size_t>(2, ((size_t)96 << 30) / (nn * sizeof(zd)));
         NS = (int)std::min<size_t>(t + NBLD, cap);
         PN.alloc(NBLD * nn); Fb.alloc(NBLD * nn); Finv.alloc((size_t)NS * nn);
-        Dinv.alloc(NBLD * n * PRE_NB); T1p.alloc(NBLD * n * PRE_NB); pvec.alloc(NBLD * 2 * n); d_zdag.alloc(NBLD);
+        Dinv.alloc(NBLD * n * PRE_NB); T1p.alloc(NBLD * n * PRE_NB); T2p.alloc(NBLD * n * PRE_OB); pvec.alloc(NBLD * 2 * n); d_zdag.alloc(NBLD);
         d_shift.alloc(NBLD); d_notpd.alloc(NBLD);
         zgemm_ws.alloc(std::max<size_t>((size_t)32 << 20, t * (size_t)n * r * 16));
     }
@@ -551,5 +558,11 @@ void Engine::refresh_store(const std::vector<int>& L)
     bl_add(Lr, sW1.p, (int64_t)m * K, m, 0, d_k.p, 1);
     bl_add(Lr, sV.p, (int64_t)n * K, n, 0, d_k.p, 1);
     r_factor(d_list2.p, nt, Lr, 4 * K, d_k.p, 4, 0, sRres.p, (int64_t)16 * K * K, 4 * K);
+    // H = V^* (S^* W1) = V^* W1[0:n]
+    BlockList Lv = bl_empty(n);
+    bl_add(Lv, sV.p, (int64_t)n * K, n, 0, d_k.p, 1);
+    BlockList Lw = bl_empty(n);
+    bl_add(Lw, sW1.p, (int64_t)m * K, m, 0, d_k.p, 1);
+    gram(d_list2.p, nt, Lv, Lw, K, K, sH.p, (int64_t)K * K, K, false, false);
 }
 

@@ -234,7 +234,46 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     const double EPSM_E = 2.220446049250313e-16;
     const double tau_c = P.tol_abs * nC;          // certification half-width
     bool redo_pass = false;                       // Lipschitz re-refinement: no store updates
+    pgam.assign(npts, zmake(0.0, 0.0));
+    pgok.assign(npts, 0);
+    std::vector<uint8_t> pdone(npts, 0);
+    // Upper bound of sigma_min at grid point pt from its finished neighbours q:
+    // for the unit vector x behind sigma(q), ||C(z) x||^2 = sigma(q)^2 -
+    // 2 Re(conj(z - z_q) gamma_q) + |z - z_q|^2 ||S x||^2 with gamma_q =
+    // (S x)^* C(z_q) x and ||S x|| <= 1; neighbours without gamma give the
+    // 1-Lipschitz bound sigma(q) + |z - z_q|.
+    auto nb_bound = [&](int64_t pt) -> double {
+        const int i = (int)(pt % nx), j = (int)(pt / nx);
+        double b = INFINITY;
+        for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+                if (!di && !dj) continue;
+                const int ii = i + di, jj = j + dj;
+                if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+                const int64_t q = (int64_t)jj * nx + ii;
+                if (!pdone[q]) continue;
+                const zd d = zsub(zs[pt], zs[q]);
+                double v;
+                if (pgok[q]) {
+                    v = sig[q] * sig[q] - 2.0 * (d.x * pgam[q].x + d.y * pgam[q].y) + zabs2(d);
+                    v = sqrt(std::max(v, 0.0));
+                } else {
+                    v = sig[q] + sqrt(zabs2(d));
+                }
+                b = std::min(b, v);
+            }
+        return b;
+    };
+    std::vector<int> pending;                     // tiles waiting for an inertia test
+    std::vector<char> cluster(T, 0);              // the tile's last refinement ended by the inertia test
+    std::vector<char> cert_pend(T, 0), cert_ok(T, 0);
+    std::vector<double> cert_mu(T, 0.0);
+    std::vector<int64_t> cert_since(T, 0);
     auto run_tiles = [&]() {
+    pending.clear();
+    std::fill(cert_pend.begin(), cert_pend.end(), 0);
+    std::fill(cert_ok.begin(), cert_ok.end(), 0);
+    std::fill(cluster.begin(), cluster.end(), 0);
     for (int t = 0; t < T; ++t) state[t] = tiles[t].done() ? 2 : 0;
     std::fill(esc_at.begin(), esc_at.end(), P.esc_iters);
     std::fill(site_exact.begin(), site_exact.end(), 0);
@@ -301,8 +340,11 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     launch_ritz(ra, K, st);
                     prof.end(st, pi);
                     HIPCHK(hipGetLastError());
+                    launch_job_gamma(nj, j_tile.p, d_k.p, j_G.p, (int64_t)K * r, K, sH.p, (int64_t)K * K, K, j_z.p,
+                                     j_gam.p, st);
                     HIPCHK(hipMemcpyAsync(h_acc.p, j_acc.p, nj, hipMemcpyDeviceToHost, st));
                     HIPCHK(hipMemcpyAsync(h_xi.p, j_xi.p, sizeof(double) * nj, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipMemcpyAsync(h_gamj.p, j_gam.p, sizeof(zd) * nj, hipMemcpyDeviceToHost, st));
                     HIPCHK(hipStreamSynchronize(st));
                 }
                 h_xi_keep.assign(h_xi.p, h_xi.p + nj);
@@ -314,19 +356,97 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     bool rejected = false;
                     for (size_t c = 0; c < w; ++c, ++j) {
                         if (rejected) continue;
-                        if (h_acc[j]) {
-                            int pt = tiles[t].order[tiles[t].cursor];
+                        const int pt = tiles[t].order[tiles[t].cursor];
+                        const bool guard = h_acc[j] && h_xi[j] > nb_bound(pt) * (1.0 + 1e-9) + 1e-12 * nC;
+                        if (h_acc[j] && !guard) {
                             sig[pt] = h_xi[j];
+                            pgam[pt] = h_gamj[j];
+                            pgok[pt] = 1;
+                            pdone[pt] = 1;
                             fl[pt] |= PS_FLAG_ACCEPTED;
                             stats.accepted++;
                             tiles[t].cursor++;
                         } else {
+                            // failed eq. (tolC), or passed it with a value above
+                            // what a finished neighbour's vector attains here (a
+                            // Ritz value of a larger singular value: start from
+                            // a random block instead of the recycled vectors)
                             rejected = true;
                             R.push_back(t);
-                            Rsrc.push_back(j);
+                            Rsrc.push_back(guard ? -1 : j);
+                            if (guard) stats.guard_rejects++;
                         }
                     }
                     if (!rejected && tiles[t].done()) state[t] = 2;
+                }
+                // tiles whose last refinement was ended by the inertia test are
+                // in a cluster regime, where the recycled Ritz value is often
+                // already within tau although its residual fails eq. (tolC):
+                // test it directly before starting LOBPCG
+                if (use_prec && tau_c > 0.0 && P.esc_iters > 0) {
+                    std::vector<int> ci;
+                    for (size_t i = 0; i < R.size(); ++i) {
+                        const int t = R[i], jb = Rsrc[i];
+                        if (jb < 0 || !cluster[t]) continue;
+                        const zd z = zs[tiles[t].order[tiles[t].cursor]];
+                        const double xi = h_xi_keep[jb];
+                        const double nz = nC + sqrt(zabs2(z));
+                        const double slack = 8.0 * (double)n * EPSM_E * nz * nz;
+                        if (xi > 64.0 * tau_c && 2.0 * xi * tau_c - tau_c * tau_c > 4.0 * slack) ci.push_back((int)i);
+                    }
+                    if (!ci.empty()) {
+                        std::vector<zd> cs;
+                        std::vector<double> cm;
+                        for (int i : ci) {
+                            const int t = R[i];
+                            const zd z = zs[tiles[t].order[tiles[t].cursor]];
+                            const double xi = h_xi_keep[Rsrc[i]];
+                            const double nz = nC + sqrt(zabs2(z));
+                            cs.push_back(z);
+                            cm.push_back((xi - tau_c) * (xi - tau_c) + 8.0 * (double)n * EPSM_E * nz * nz);
+                        }
+                        // the inertia tests waiting for running refinements join this batch
+                        std::vector<int> pj;
+                        for (int t : pending)
+                            if (cert_pend[t] && state[t] == 1) {
+                                pj.push_back(t);
+                                cs.push_back(h_zt[t]);
+                                cm.push_back(cert_mu[t]);
+                            }
+                        pending.clear();
+                        auto tc0 = now();
+                        std::vector<char> pd;
+                        build_precond(cs, &cm, &pd, true, true);
+                        stats.cert_tests += (int64_t)cs.size();
+                        stats.t_precond_ms += ms(tc0, now());
+                        for (size_t q = 0; q < pj.size(); ++q) {
+                            const int t = pj[q];
+                            cert_pend[t] = 0;
+                            if (pd[ci.size() + q]) cert_ok[t] = 1;
+                            else { cert_fail[t]++; cert_next[t] = lob_it[t] + 10; }
+                        }
+                        std::vector<char> drop(R.size(), 0);
+                        for (size_t q = 0; q < ci.size(); ++q) {
+                            if (!pd[q]) continue;
+                            const int i = ci[q], t = R[i], jb = Rsrc[i];
+                            const int pt = tiles[t].order[tiles[t].cursor];
+                            sig[pt] = h_xi_keep[jb];
+                            pgam[pt] = h_gamj[jb];
+                            pgok[pt] = 1;
+                            pdone[pt] = 1;
+                            fl[pt] |= PS_FLAG_ACCEPTED | PS_FLAG_CERTIFIED;
+                            stats.accepted++;
+                            stats.certified++;
+                            tiles[t].cursor++;
+                            drop[i] = 1;
+                            state[t] = tiles[t].done() ? 2 : 0;
+                        }
+                        std::vector<int> R2, S2;
+                        for (size_t i = 0; i < R.size(); ++i)
+                            if (!drop[i]) { R2.push_back(R[i]); S2.push_back(Rsrc[i]); }
+                        R.swap(R2);
+                        Rsrc.swap(S2);
+                    }
                 }
             } else {
                 for (int t : idle) { R.push_back(t); Rsrc.push_back(-1); }
@@ -440,7 +560,17 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             HIPCHK(hipMemcpyAsync(d_z.p, h_z.p, sizeof(zd) * T, hipMemcpyHostToDevice, st));
             step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
             lob_start(R, step_seed);
-            for (int t : R) { state[t] = 1; esc_at[t] = P.esc_iters; site_exact[t] = 0; }
+            for (int t : R) {
+                state[t] = 1;
+                cert_pend[t] = 0;
+                cert_ok[t] = 0;
+                esc_at[t] = P.esc_iters;
+                site_exact[t] = 0;
+                stag[t] = 0;
+                cert_next[t] = 0;
+                cert_fail[t] = 0;
+                lob_prev[t] = INFINITY;
+            }
         }
         // ---- C. one LOBPCG iteration for every running tile
         std::vector<int> run;
@@ -455,81 +585,154 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         std::vector<int> fin, okv;
         step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
         lob_step(run, step_seed, fin, okv);
-        // ---- C'. slow refinements (every esc_iters iterations without
-        // convergence).  A refinement whose smallest Ritz value xi is large
-        // enough for the test to resolve it gets two factorizations at its own
-        // point: N(z) - mu0 I with mu0 = (xi - tau)^2 + slack, whose
-        // positive definiteness (all Cholesky pivots positive) certifies
-        // sigma_min >= xi - tau by Sylvester's law of inertia, so xi is
-        // accepted; and N(z) - mu1 I with mu1 = (xi - 64 tau)^2, which, when
-        // positive definite, becomes the refinement's preconditioner: a shift
-        // just below the bottom of a cluster of singular values separates the
-        // cluster.  Smaller xi (the test cannot resolve it) get the exact site
-        // N(z) + delta I instead of a shared one.  slack bounds the rounding
-        // of forming N(z) and of the Cholesky factorization.
+        // ---- C'. slow refinements.  In a cluster of small singular values
+        // the smallest Ritz value xi converges long before the residual of
+        // eq. (tolSVD) does.  When xi has stalled (two steps that lower it by
+        // less than tau / 10), and every esc_iters iterations, a refinement
+        // whose xi is large enough for the test to resolve gets the inertia
+        // test at its own point: N(z) - mu0 I with mu0 = (xi - tau)^2 + slack
+        // positive definite (every Cholesky pivot positive) certifies
+        // sigma_min >= xi - tau by Sylvester's law of inertia, and xi is
+        // accepted.  After two failed tests it gets a shifted preconditioner
+        // (N(z) - mu I)^{-1}, mu = (xi - 64 tau)^2, else (xi - 4096 tau)^2,
+        // whichever is positive definite: a shift just below the bottom of
+        // the cluster separates it.  Refinements with smaller xi (the test
+        // cannot resolve them) get an exact site N(z) + delta I at their own
+        // point instead.  slack bounds the rounding of forming N(z) and of the
+        // Cholesky factorization.
         if (use_prec && P.esc_iters > 0) {
             std::vector<char> isfin(T, 0);
             for (int t : fin) isfin[t] = 1;
-            std::vector<zd> sites;
-            std::vector<double> mus;
-            std::vector<int> own, kind;
+            std::vector<zd> fsites;
+            std::vector<double> fmus;
+            std::vector<int> fown, fkind;
             for (int t : run) {
-                if (isfin[t] || lob_it[t] < esc_at[t]) continue;
-                esc_at[t] = lob_it[t] + P.esc_iters;
+                if (isfin[t]) continue;
+                if (cert_pend[t]) continue;
                 const zd z = h_zt[t];
                 const double xi = lob_xi[t];
+                if (lob_prev[t] - xi <= 0.1 * tau_c) stag[t]++;
+                else stag[t] = 0;
+                lob_prev[t] = xi;
                 const double nz = nC + sqrt(zabs2(z));
                 const double slack = 8.0 * (double)n * EPSM_E * nz * nz;
-                if (tau_c > 0.0 && xi > 64.0 * tau_c && 2.0 * xi * tau_c - tau_c * tau_c > 4.0 * slack) {
-                    sites.push_back(z); mus.push_back((xi - tau_c) * (xi - tau_c) + slack); own.push_back(t);
-                    kind.push_back(0);
-                    sites.push_back(z); mus.push_back((xi - 64.0 * tau_c) * (xi - 64.0 * tau_c)); own.push_back(t);
-                    kind.push_back(1);
-                } else if (!site_exact[t]) {
-                    sites.push_back(z); mus.push_back(0.0); own.push_back(t); kind.push_back(2);
+                const bool resolvable =
+                    tau_c > 0.0 && xi > 64.0 * tau_c && 2.0 * xi * tau_c - tau_c * tau_c > 4.0 * slack;
+                const bool period = lob_it[t] >= esc_at[t];
+                if (period) esc_at[t] = lob_it[t] + P.esc_iters;
+                if (resolvable) {
+                    if ((stag[t] >= 2 && lob_it[t] >= cert_next[t]) || period) {
+                        cert_pend[t] = 1;
+                        cert_mu[t] = (xi - tau_c) * (xi - tau_c) + slack;
+                        cert_since[t] = loops;
+                        pending.push_back(t);
+                    }
+                    if (period && cert_fail[t] >= 2 && !site_exact[t]) {
+                        fsites.push_back(z); fmus.push_back((xi - 64.0 * tau_c) * (xi - 64.0 * tau_c));
+                        fown.push_back(t); fkind.push_back(1);
+                        if (xi > 4096.0 * tau_c) {
+                            fsites.push_back(z); fmus.push_back((xi - 4096.0 * tau_c) * (xi - 4096.0 * tau_c));
+                            fown.push_back(t); fkind.push_back(3);
+                        }
+                    }
+                } else if (period && !site_exact[t]) {
+                    fsites.push_back(z); fmus.push_back(0.0); fown.push_back(t); fkind.push_back(2);
                 }
             }
-            if (!sites.empty()) {
-                auto te0 = now();
+            auto te0 = now();
+            std::vector<char> certified(T, 0);
+            for (int t : run)
+                if (cert_ok[t]) {
+                    cert_ok[t] = 0;
+                    if (!isfin[t]) certified[t] = 1;
+                }
+            // inertia tests wait (while their refinements keep iterating) until
+            // a full batch is pending, the oldest has waited 4 steps, or
+            // nothing else is running
+            {
+                std::vector<int> still;
+                for (int t : pending)
+                    if (cert_pend[t] && state[t] == 1 && !isfin[t]) still.push_back(t);
+                    else cert_pend[t] = 0;
+                pending.swap(still);
+                int nrun = 0;
+                for (int t : run) nrun += !isfin[t];
+                bool flush = (int)pending.size() >= NBLD || (int)pending.size() >= nrun;
+                for (int t : pending) flush |= loops - cert_since[t] >= 6;
+                if (flush && !pending.empty()) {
+                    std::vector<zd> cs;
+                    std::vector<double> cm;
+                    for (int t : pending) { cs.push_back(h_zt[t]); cm.push_back(cert_mu[t]); }
+                    std::vector<char> pd;
+                    build_precond(cs, &cm, &pd, true, true);
+                    stats.cert_tests += (int64_t)cs.size();
+                    for (size_t i = 0; i < pending.size(); ++i) {
+                        const int t = pending[i];
+                        cert_pend[t] = 0;
+                        if (pd[i]) certified[t] = 1;
+                        else { cert_fail[t]++; cert_next[t] = lob_it[t] + 10; }
+                    }
+                    pending.clear();
+                }
+            }
+            if (!fsites.empty()) {
                 std::vector<char> pd;
-                std::vector<int> got = build_precond(sites, &mus, &pd, true);
-                std::vector<char> certified(T, 0);
-                for (size_t i = 0; i < sites.size(); ++i)
-                    if (kind[i] == 0 && got[i] >= 0 && pd[i]) certified[own[i]] = 1;
-                for (size_t i = 0; i < sites.size(); ++i) {
-                    const int t = own[i], sl = got[i];
+                std::vector<int> got = build_precond(fsites, &fmus, &pd, true);
+                std::vector<int> pick(T, -1);
+                // preference: the closest shift (kind 1), then kind 3, then the exact site
+                auto rank = [](int kd) { return kd == 1 ? 0 : (kd == 3 ? 1 : 2); };
+                for (size_t i = 0; i < fsites.size(); ++i) {
+                    const int t = fown[i];
+                    const bool usable = got[i] >= 0 && (fkind[i] == 2 || pd[i]) && !certified[t];
+                    if (usable && (pick[t] < 0 || rank(fkind[i]) < rank(fkind[pick[t]]))) pick[t] = (int)i;
+                }
+                for (size_t i = 0; i < fsites.size(); ++i) {
+                    const int t = fown[i], sl = got[i];
                     if (sl < 0) continue;
-                    bool take = !certified[t] && ((kind[i] == 1 && pd[i]) || kind[i] == 2);
-                    if (take) {
+                    if (pick[t] == (int)i) {
                         if (tile_slot[t] >= 0) slot_ref[tile_slot[t]]--;
                         tile_slot[t] = sl;
                         slot_ref[sl]++;
                         usek[t] = 1;
-                        site_exact[t] = 1;
+                        if (fkind[i] != 3) site_exact[t] = 1;
                     } else {
-                        slot_valid[sl] = 0;       // certificate-only or indefinite factor
+                        slot_valid[sl] = 0;
                     }
                 }
-                for (int t = 0; t < T; ++t)
-                    if (certified[t]) {
-                        fin.push_back(t);
-                        okv.push_back(2);
-                        lob_sigma[t] = lob_xi[t];
-                        stats.certified++;
-                    }
-                stats.t_precond_ms += ms(te0, now());
             }
+            for (int t = 0; t < T; ++t)
+                if (certified[t]) {
+                    fin.push_back(t);
+                    okv.push_back(2);
+                    lob_sigma[t] = lob_xi[t];
+                    stats.certified++;
+                }
+            stats.t_precond_ms += ms(te0, now());
         }
         auto t3 = now();
         t_lob += ms(t1, t3) - 0.0 * ms(t1, t2);
-        // ---- D. finished tiles: record sigma, update their recycled store
+        // ---- D. finished tiles: record sigma and gamma = x^* C(z) x of the
+        // first Ritz vector, update their recycled store
+        if (!fin.empty()) {
+            upload_list(fin, d_list2);
+            launch_tile_dot0(d_list2.p, (int)fin.size(), S.p, sS, CS.p, (int64_t)m * 3 * r, n, d_gamt.p, st);
+            HIPCHK(hipMemcpyAsync(h_gamt.p, d_gamt.p, sizeof(zd) * T, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
         for (size_t i = 0; i < fin.size(); ++i) {
             int t = fin[i];
+            {
+                const int pt0 = tiles[t].order[tiles[t].cursor];
+                pgam[pt0] = h_gamt[t];
+                pgok[pt0] = 1;
+                pdone[pt0] = 1;
+            }
             if (use_prec && tile_slot[t] >= 0) { slot_ref[tile_slot[t]]--; tile_slot[t] = -1; }
             int pt = tiles[t].order[tiles[t].cursor];
             sig[pt] = lob_sigma[t];
             fl[pt] |= PS_FLAG_REFINED;
             if (okv[i] == 2) fl[pt] |= PS_FLAG_CERTIFIED;
+            cluster[t] = (okv[i] == 2) ? 1 : 0;
             if (!okv[i]) fl[pt] |= PS_FLAG_UNCERTIFIED;
             else fl[pt] &= (uint8_t)~PS_FLAG_UNCERTIFIED;
             stats.refined++;
@@ -551,31 +754,21 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     }
     };
     run_tiles();
-    // Lipschitz pass: sigma_min is 1-Lipschitz in z and every value computed
-    // here is a Ritz value, an upper bound of sigma_min, so a point with
-    // sigma(z) > sigma(z') + |z - z'| for one of its eight grid neighbours z'
-    // is certainly too high (a Ritz value that converged to a larger singular
-    // value).  Such points are refined again from a random start block, one
-    // point per tile, without touching any recycled store; repeated while
-    // violations remain (at most 4 passes).
+    // Neighbour pass: every value computed here is a Ritz value, an upper
+    // bound of sigma_min, and each finished neighbour gives an upper bound of
+    // sigma_min at z (nb_bound: the norm of C(z) on the neighbour's vector,
+    // or the 1-Lipschitz bound), so a point whose value exceeds one of them is
+    // certainly too high (a Ritz value of a larger singular value).  Such
+    // points are refined again from a random start block, one point per tile,
+    // without touching any recycled store; repeated while violations remain
+    // (at most 4 passes).
     if (P.lipschitz) {
-        auto zpt = [&](int64_t p) { return zs[p]; };
         for (int pass = 0; pass < 4; ++pass) {
             std::vector<int> viol;
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
                     const int64_t p = (int64_t)j * nx + i;
-                    bool v = false;
-                    for (int dj = -1; dj <= 1 && !v; ++dj)
-                        for (int di = -1; di <= 1 && !v; ++di) {
-                            if (!di && !dj) continue;
-                            const int ii = i + di, jj = j + dj;
-                            if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
-                            const int64_t q = (int64_t)jj * nx + ii;
-                            const double d = sqrt(zabs2(zsub(zpt(p), zpt(q))));
-                            v = sig[p] > sig[q] + d * (1.0 + 1e-12) + 1e-13 * nC;
-                        }
-                    if (v) viol.push_back((int)p);
+                    if (sig[p] > nb_bound(p) * (1.0 + 1e-9) + 1e-12 * nC) viol.push_back((int)p);
                 }
             if (viol.empty()) break;
             stats.lipschitz_redo += (int64_t)viol.size();

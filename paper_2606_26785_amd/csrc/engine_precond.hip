@@ -134,7 +134,7 @@ void Engine::precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, z
 // F^{-1} F^{-*}.  Up to NBLD sites are built at once in the staging blocks
 // and copied into free slots (least recently used first).
 std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::vector<double>* mu,
-                                       std::vector<char>* pd, bool priv)
+                                       std::vector<char>* pd, bool priv, bool cert_only)
 {
     std::vector<int> out;
     if (pd) pd->assign(sites.size(), 0);
@@ -162,40 +162,66 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
         HIPCHK(hipMemcpyAsync(d_shift.p, h_shift.p, sizeof(double) * nb, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemsetAsync(d_notpd.p, 0, sizeof(int) * nb, st));
         launch_form_normal(dl, nb, CtC.p, op.A.p, m, op.AH.p, n, d_zdag.p, d_shift.p, PN.p, nn, st);
-        launch_zero_tiles(dl, nb, Fb.p, nn, nn, st);
-        for (int64_t k0 = 0; k0 < n; k0 += PRE_NB) {
-            const int kb = (int)std::min<int64_t>(PRE_NB, n - k0);
-            launch_chol_diag(dl, nb, PN.p, nn, n, k0, kb, Dinv.p, (int64_t)n * PRE_NB, Fb.p, nn, 1e-2 * delta,
-                             d_notpd.p, st);
-            const int64_t k1 = k0 + kb, rest = n - k1;
-            if (rest > 0) {
-                // row panel: R[k, k1:] = R_kk^{-*} A[k, k1:]
-                zgemm(dl, nb, kb, rest, kb, Dinv.p + k0, n, (int64_t)n * PRE_NB, 1, PN.p + k0 + k1 * n, n, nn,
-                      PN.p + k0 + k1 * n, n, nn, 1.0, 0.0);
-                // trailing Hermitian update (upper part)
-                zgemm(dl, nb, rest, rest, kb, PN.p + k0 + k1 * n, n, nn, 1, PN.p + k0 + k1 * n, n, nn,
-                      PN.p + k1 + k1 * n, n, nn, -1.0, 1.0, 1);
+        if (!cert_only) launch_zero_tiles(dl, nb, Fb.p, nn, nn, st);
+        // two-level blocked Cholesky: outer blocks of PRE_OB columns updated
+        // right-looking (one rank-PRE_OB trailing product per outer block,
+        // so the trailing matrix is streamed n / PRE_OB times), inner blocks
+        // of PRE_NB rows updated left-looking within the outer block row
+        for (int64_t K0 = 0; K0 < n; K0 += PRE_OB) {
+            const int64_t K1 = std::min<int64_t>(n, K0 + PRE_OB);
+            for (int64_t k0 = K0; k0 < K1; k0 += PRE_NB) {
+                const int kb = (int)std::min<int64_t>(PRE_NB, K1 - k0);
+                if (k0 > K0) {
+                    // A[k, k0:] -= R[K0:k0, k]^* R[K0:k0, k0:]
+                    zgemm(dl, nb, kb, n - k0, k0 - K0, PN.p + K0 + k0 * n, n, nn, 1, PN.p + K0 + k0 * n, n, nn,
+                          PN.p + k0 + k0 * n, n, nn, -1.0, 1.0);
+                }
+                // diagonal block and row panel R[k, k1:] = R_kk^{-*} A[k, k1:] in one launch
+                launch_chol_step(dl, nb, PN.p, nn, n, k0, kb, cert_only ? nullptr : Dinv.p, (int64_t)n * PRE_NB,
+                                 cert_only ? nullptr : Fb.p, nn, 1e-2 * delta, d_notpd.p, st);
+                if (!cert_only && k0 > K0) {
+                    // F^{-1}[K0:k0, k] = -F^{-1}[K0:k0, K0:k0] R[K0:k0, k] R_kk^{-1}
+                    zgemm(dl, nb, k0 - K0, kb, k0 - K0, Fb.p + K0 + K0 * n, n, nn, 0, PN.p + K0 + k0 * n, n, nn,
+                          T1p.p, n, (int64_t)n * PRE_NB, 1.0, 0.0);
+                    zgemm(dl, nb, k0 - K0, kb, kb, T1p.p, n, (int64_t)n * PRE_NB, 0, Dinv.p + k0, n,
+                          (int64_t)n * PRE_NB, Fb.p + K0 + k0 * n, n, nn, -1.0, 0.0);
+                }
             }
-            if (k0 > 0) {
-                // F^{-1}[0:k0, k-block] = -F^{-1}[0:k0, 0:k0] R[0:k0, k-block] R_kk^{-1}
-                zgemm(dl, nb, k0, kb, k0, Fb.p, n, nn, 0, PN.p + k0 * n, n, nn, T1p.p, n, (int64_t)n * PRE_NB, 1.0,
-                      0.0);
-                zgemm(dl, nb, k0, kb, kb, T1p.p, n, (int64_t)n * PRE_NB, 0, Dinv.p + k0, n, (int64_t)n * PRE_NB,
-                      Fb.p + k0 * n, n, nn, -1.0, 0.0);
+            if (K1 < n) {
+                // trailing Hermitian update (upper part), rank K1 - K0
+                zgemm(dl, nb, n - K1, n - K1, K1 - K0, PN.p + K0 + K1 * n, n, nn, 1, PN.p + K0 + K1 * n, n, nn,
+                      PN.p + K1 + K1 * n, n, nn, -1.0, 1.0, 1);
+            }
+            if (!cert_only && K0 > 0) {
+                // F^{-1}[0:K0, K] = -F^{-1}[0:K0, 0:K0] (R[0:K0, K] F^{-1}[K, K])
+                zgemm(dl, nb, K0, K1 - K0, K1 - K0, PN.p + K0 * n, n, nn, 0, Fb.p + K0 + K0 * n, n, nn, T2p.p, n,
+                      (int64_t)n * PRE_OB, 1.0, 0.0);
+                zgemm(dl, nb, K0, K1 - K0, K0, Fb.p, n, nn, 0, T2p.p, n, (int64_t)n * PRE_OB, Fb.p + K0 * n, n, nn,
+                      -1.0, 0.0, 0, 1);
             }
         }
         HIPCHK(hipGetLastError());
+        if (cert_only) {
+            h_notpd.alloc((size_t)nb + 8);
+            HIPCHK(hipMemcpyAsync(h_notpd.p, d_notpd.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int i = 0; i < nb; ++i) {
+                if (pd) (*pd)[b0 + i] = h_notpd[i] == 0;
+                out.push_back(-1);
+            }
+            continue;
+        }
         // gamma^2 = lambda_max(F^{-1} F^{-*}) by power iteration
         const int64_t sp = 2 * n;
         launch_randfill(dl, nb, pvec.p, sp, n, n, 1, nullptr, 0x7a11ull, st);
         std::vector<double> g2(nb, 0.0);
-        for (int it = 0; it < 30; ++it) {
+        for (int it = 0; it < 12; ++it) {
             zgemm(dl, nb, n, 1, n, Fb.p, n, nn, 1, pvec.p, n, sp, pvec.p + n, n, sp, 1.0, 0.0, 0, 2);
             zgemm(dl, nb, n, 1, n, Fb.p, n, nn, 0, pvec.p + n, n, sp, pvec.p, n, sp, 1.0, 0.0, 0, 1);
             BlockList Lp = bl_empty(n);
             bl_add(Lp, pvec.p, sp, n, 1, nullptr, 0);
             colnorm2(dl, nb, Lp, 1, nrm2.p, 3 * r);
-            if (it == 29) {
+            if (it == 11) {
                 HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * nb * 3 * r, hipMemcpyDeviceToHost, st));
                 h_notpd.alloc((size_t)nb + 8);
                 HIPCHK(hipMemcpyAsync(h_notpd.p, d_notpd.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));

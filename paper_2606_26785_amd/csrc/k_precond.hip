@@ -104,6 +104,103 @@ void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n
                        strideF, floor_piv, notpd);
 }
 
+// One step of the blocked Cholesky, fused: every workgroup of the grid
+// (chunk, matrix) factors the diagonal block A_kk (kb <= 32, upper triangle
+// read) redundantly in LDS and forms X = R_kk^{-1}; chunk 0 writes X into
+// Dinv and into the diagonal block of Finv (when non-null) and raises notpd
+// on a non-positive pivot; chunk c >= 1 turns columns
+// k1 + (c - 1) PANEL_W ... of the block row into the row panel of the factor,
+// A[k, cols] <- X^* A[k, cols] (= R_kk^{-*} A[k, cols]).  Replaces a
+// single-workgroup diagonal kernel plus a separate panel product per step.
+#define PANEL_W 64
+__global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_t strideA, int64_t n, int64_t k0,
+                                                  int kb, zd* Dinv, int64_t strideD, zd* Finv, int64_t strideF,
+                                                  double floor_piv, int* notpd)
+{
+    __shared__ zd R[32][33];
+    __shared__ zd X[32][33];
+    __shared__ zd Pn[32][PANEL_W + 1];
+    __shared__ double piv;
+    __shared__ int bad;
+    const int tile = list[blockIdx.y];
+    const int chunk = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t k1 = k0 + kb;
+    const int64_t c0 = k1 + (int64_t)(chunk - 1) * PANEL_W;
+    if (chunk > 0 && c0 >= n) return;
+    zd* Ab = A + (size_t)tile * strideA;
+    if (tid == 0) bad = 0;
+    for (int e = tid; e < kb * kb; e += NT) {
+        int i = e % kb, j = e / kb;
+        R[i][j] = (i <= j) ? Ab[k0 + i + (k0 + j) * n] : zmake(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+        if (tid == 0) {
+            double d = R[j][j].x;
+            if (!(d > 0.0)) bad = 1;
+            if (!(d > floor_piv)) d = floor_piv;
+            piv = sqrt(d);
+        }
+        __syncthreads();
+        const double p = piv;
+        for (int c = j + tid; c < kb; c += NT) R[j][c] = (c == j) ? zmake(p, 0.0) : zscale(R[j][c], 1.0 / p);
+        __syncthreads();
+        for (int e = tid; e < kb * kb; e += NT) {
+            int a2 = e % kb, c = e / kb;
+            if (a2 > j && c >= a2) R[a2][c] = zsub(R[a2][c], zcmul(R[j][a2], R[j][c]));
+        }
+        __syncthreads();
+    }
+    // X = R^{-1} (upper), one thread per column
+    for (int c = tid; c < kb; c += NT) {
+        for (int i = kb - 1; i >= 0; --i) {
+            if (i > c) { X[i][c] = zmake(0.0, 0.0); continue; }
+            zd s = zmake(i == c ? 1.0 : 0.0, 0.0);
+            for (int l = i + 1; l <= c; ++l) s = zsub(s, zmul(R[i][l], X[l][c]));
+            X[i][c] = zscale(s, 1.0 / R[i][i].x);
+        }
+    }
+    __syncthreads();
+    if (chunk == 0) {
+        if (tid == 0 && bad) notpd[tile] = 1;
+        zd* Db = Dinv ? Dinv + (size_t)tile * strideD + k0 : nullptr;
+        zd* Fb = Finv ? Finv + (size_t)tile * strideF + k0 + k0 * n : nullptr;
+        // (R_kk is not written back: the other workgroups of this launch
+        // read the unfactored block, and later steps need only X and the
+        // row panels)
+        for (int e = tid; e < kb * kb; e += NT) {
+            int i = e % kb, j = e / kb;
+            if (Db) Db[i + (int64_t)j * n] = X[i][j];
+            if (Fb) Fb[i + (int64_t)j * n] = X[i][j];
+        }
+        return;
+    }
+    const int w = (int)((n - c0) < PANEL_W ? (n - c0) : PANEL_W);
+    for (int e = tid; e < kb * PANEL_W; e += NT) {
+        int i = e % kb, c = e / kb;
+        Pn[i][c] = (c < w) ? Ab[k0 + i + (c0 + c) * n] : zmake(0.0, 0.0);
+    }
+    __syncthreads();
+    // out[i][c] = sum_{l <= i} conj(X[l][i]) Pn[l][c]
+    for (int e = tid; e < kb * w; e += NT) {
+        int i = e % kb, c = e / kb;
+        zd s = zmake(0.0, 0.0);
+        for (int l = 0; l <= i; ++l) s = zadd(s, zcmul(X[l][i], Pn[l][c]));
+        Ab[k0 + i + (c0 + c) * n] = s;
+    }
+}
+
+void launch_chol_step(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
+                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s)
+{
+    if (nt <= 0) return;
+    const int64_t rest = n - (k0 + kb);
+    const unsigned chunks = 1 + (unsigned)((rest + PANEL_W - 1) / PANEL_W);
+    hipLaunchKernelGGL(k_chol_step, dim3(chunks, nt), dim3(NT), 0, s, list, A, strideA, n, k0, kb, Dinv, strideD,
+                       Finv, strideF, floor_piv, notpd);
+}
+
 // batched conjugate transpose of square n x n matrices (per tile)
 __global__ void k_conj_transpose_b(const int* list, const zd* A, int64_t stride, int64_t n, zd* B)
 {

@@ -356,3 +356,66 @@ void launch_zero(zd* A, int64_t count, hipStream_t s)
     if (count <= 0) return;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, s, A, count);
 }
+
+// gamma[t] = x^* y[0:n] for the first columns x of X and y of Y of each tile
+// (with y = C(z) x this is (S x)^* C(z) x, the first-order coefficient of
+// ||C(z') x|| in z' - z)
+__global__ void __launch_bounds__(256) k_tile_dot0(const int* list, const zd* X, int64_t xs, const zd* Y, int64_t ys,
+                                                   int64_t n, zd* out)
+{
+    __shared__ double red[4];
+    const int t = list[blockIdx.x];
+    const zd* x = X + (size_t)t * xs;
+    const zd* y = Y + (size_t)t * ys;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        zd a = x[i], b = y[i];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+    }
+    re = block_sum(re, red);
+    im = block_sum(im, red);
+    if (threadIdx.x == 0) out[t] = zmake(re, im);
+}
+
+void launch_tile_dot0(const int* list, int ntiles, const zd* X, int64_t xs, const zd* Y, int64_t ys, int64_t n,
+                      zd* out, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_tile_dot0, dim3(ntiles), dim3(256), 0, s, list, X, xs, Y, ys, n, out);
+}
+
+// gamma_j = g^* H g - z_j for every Ritz job j, g the job's first Ritz
+// coefficient vector (unit, k entries) and H = V^* S^* C V of its tile
+// (k x k), so gamma_j = (S x)^* C(z_j) x for the Ritz vector x = V g
+__global__ void __launch_bounds__(64) k_job_gamma(int njobs, const int* job_tile, const int* kdim, const zd* G,
+                                                  int64_t sG, int ldG, const zd* H, int64_t sH, int ldH,
+                                                  const zd* z, zd* out)
+{
+    __shared__ double red[1];
+    const int j = blockIdx.x;
+    if (j >= njobs) return;
+    const int t = job_tile[j];
+    const int k = kdim[t];
+    const zd* g = G + (size_t)j * sG;
+    const zd* Hb = H + (size_t)t * sH;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < k; i += 64) {
+        zd s = zmake(0.0, 0.0);
+        for (int c = 0; c < k; ++c) zfma(s, Hb[i + (size_t)c * ldH], g[c]);
+        zd gi = g[i];
+        re += gi.x * s.x + gi.y * s.y;
+        im += gi.x * s.y - gi.y * s.x;
+    }
+    re = block_sum(re, red);
+    im = block_sum(im, red);
+    if (threadIdx.x == 0) out[j] = (k > 0) ? zmake(re - z[j].x, im - z[j].y) : zmake(0.0, 0.0);
+}
+
+void launch_job_gamma(int njobs, const int* job_tile, const int* kdim, const zd* G, int64_t sG, int ldG, const zd* H,
+                      int64_t sH, int ldH, const zd* z, zd* out, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_job_gamma, dim3(njobs), dim3(64), 0, s, njobs, job_tile, kdim, G, sG, ldG, H, sH, ldH, z,
+                       out);
+}

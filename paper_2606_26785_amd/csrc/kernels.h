@@ -132,6 +132,10 @@ void launch_zaxpy_tile(const int* list, int ntiles, const zd* z, int conjz, zd* 
                        int64_t ldy, const zd* X, int64_t xstride, int64_t ldx, int64_t rows, int cols,
                        hipStream_t s);
 // R = Y - X diag(xi^2)
+void launch_tile_dot0(const int* list, int ntiles, const zd* X, int64_t xs, const zd* Y, int64_t ys, int64_t n,
+                      zd* out, hipStream_t s);
+void launch_job_gamma(int njobs, const int* job_tile, const int* kdim, const zd* G, int64_t sG, int ldG, const zd* H,
+                      int64_t sH, int ldH, const zd* z, zd* out, hipStream_t s);
 void launch_resid_xi(const int* list, int ntiles, zd* Y, int64_t ystride, int64_t ldy, const zd* X,
                      int64_t xstride, int64_t ldx, const double* xi, int ldxi, int64_t rows, int cols,
                      hipStream_t s);
@@ -190,9 +194,12 @@ void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s);
 
 // dense base preconditioner (k_precond.hip)
 #define PRE_NB 32
+#define PRE_OB 128
 void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int64_t ldc, const zd* CH,
                         int64_t n, const zd* zdag, const double* shift, zd* N, int64_t strideN, hipStream_t s);
 void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
+                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s);
+void launch_chol_step(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
                       int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s);
 void launch_conj_transpose_b(const int* list, int nt, const zd* A, int64_t stride, int64_t n, zd* B, hipStream_t s);
 void launch_zero_tiles(const int* list, int nt, zd* A, int64_t stride, int64_t count, hipStream_t s);

@@ -47,7 +47,7 @@ void ps_default_params(ps_params* p)
     p->rho_small = 1e-5;
     p->profile = 0;
     p->verbose = 0;
-    p->tol_abs = 5e-9;
+    p->tol_abs = 8e-9;
     p->esc_iters = 30;
     p->lipschitz = 1;
 }
