@@ -41,6 +41,7 @@ def main():
     ap.add_argument("--tiles-x", type=int, default=0)
     ap.add_argument("--tiles-y", type=int, default=0)
     ap.add_argument("--batch", type=int, default=20)
+    ap.add_argument("--save-sigma", default="", help="write the grid's sigma and flags to this .npy")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path shards by grid tile; see DESIGN.md)",
@@ -80,8 +81,8 @@ def main():
     st = res.stats
 
     # dominant kernel class by event-timed device time
-    names = ["operator_apply_zgemm_mfma", "precond_zgemm_mfma", "ritz_jacobi"]
-    c = int(np.argmax(st["k_ms"][:3]))
+    names = ["operator_apply_zgemm_mfma", "precond_apply_zgemm_mfma", "ritz_jacobi", "factorization_zgemm_mfma"]
+    c = int(np.argmax([st["k_ms"][i] if i != 2 else 0.0 for i in range(4)]))
     launches = st["k_launches"][c]
     roofline = None
     if launches > 0 and st["k_ms"][c] > 0:
@@ -92,7 +93,7 @@ def main():
                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": names[c],
                     "launches": int(launches), "avg_launch_ms": avg_ms,
                     "flops_per_launch": fl, "bytes_per_launch": st["k_bytes"][c] / launches,
-                    "device_ms_by_class": dict(zip(names, st["k_ms"][:3]))}
+                    "device_ms_by_class": dict(zip(names, st["k_ms"][:4]))}
 
     plain = None
     if not args.no_plain:
@@ -109,6 +110,9 @@ def main():
                  "lobpcg_iters": resp.stats["lobpcg_iters"], "uncertified": resp.stats["uncertified"]}
         matp.close()
         log("plain solver: %d points in %.2f s" % (g * g, tp))
+
+    if args.save_sigma:
+        np.save(args.save_sigma, np.stack([res.sigma, res.flags.astype(np.float64)]))
 
     # full-grid parity against the stored oracle values (tests/golden), when present
     parity = None

@@ -103,7 +103,7 @@ typedef struct {
     double eta_abs;     /* absolute acceptance: a smallest Ritz value xi_1 <=
                            eta_abs ||C||_2 is accepted, because sigma_min lies
                            in [0, xi_1] (Ritz values bound it from above)
-                           (default 1e-9; 0 disables; at most 1e-8) */
+                           (default 8e-9; 0 disables; at most 1e-8) */
     double rho_small;   /* refined points whose recycled Ritz value is below
                            rho_small ||M(z)|| run LOBPCG with K = I and build no
                            base preconditioner (default 1e-5) */
@@ -145,13 +145,16 @@ typedef struct {
     int64_t lipschitz_redo;/* points refined again by the neighbour pass */
     int64_t guard_rejects; /* points that passed eq. (tolC) above a neighbour bound */
     int64_t cert_tests;    /* inertia tests (Cholesky of N(z) - mu I) run */
+    int64_t builds_shared; /* preconditioner sites built for sharing (rebuild rule) */
+    int64_t builds_private;/* sites built for one slow refinement (shifted or exact) */
     double t_total_ms;     /* wall time of ps_eval */
     double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
     /* with profile = 1: event-timed kernel classes (launches, device ms,
      * algorithmic flops and bytes).  Class 0: operator applies C X, C^* Y
      * (dense: matrix-core GEMM + split-K reduction; CSR: SpMM); class 1:
-     * preconditioner GEMMs (construction and K^{-1} W); class 2: Ritz
-     * extraction (per-point Jacobi SVD + residual). */
+     * preconditioner applies K^{-1} W; class 2: Ritz extraction (per-point
+     * Jacobi SVD + residual); class 3: matrix-core products of the
+     * factorizations (preconditioner sites and inertia tests). */
     int64_t k_launches[4];
     double k_ms[4];
     double k_flops[4];

@@ -53,7 +53,7 @@ class ps_params(ctypes.Structure):
 class ps_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "points", "accepted", "refined", "uncertified", "lobpcg_iters", "proj_accepted",
-        "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds", "certified", "lipschitz_redo", "guard_rejects", "cert_tests")] + \
+        "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds", "certified", "lipschitz_redo", "guard_rejects", "cert_tests", "builds_shared", "builds_private")] + \
         [(n, ctypes.c_double) for n in ("t_total_ms", "t_ritz_ms", "t_lobpcg_ms", "t_update_ms",
                                         "t_precond_ms")] + \
         [("k_launches", ctypes.c_int64 * 4), ("k_ms", ctypes.c_double * 4), ("k_flops", ctypes.c_double * 4),

@@ -193,6 +193,7 @@ struct Engine {
                double beta, int upper = 0, int tri = 0, const int* gmap = nullptr, int cw = 0);
 
     KProf prof;
+    int zgemm_cls = 1;        // profiling class of zgemm launches (3 inside factorizations)
     ps_stats stats{};
     std::vector<Tile> tiles;
     std::vector<zd> zs;       // grid points of the current eval

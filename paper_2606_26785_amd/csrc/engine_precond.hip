@@ -52,7 +52,7 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
     double fl = 8.0 * (double)M * N * Kd * nt * ((upper || tri) ? 0.5 : 1.0);
     double by = 16.0 * nt * ((double)M * Kd * (tri ? 0.5 : 1.0) + (double)Kd * N +
                              (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
-    int pi = prof.begin(st, 1, fl, by);
+    int pi = prof.begin(st, zgemm_cls, fl, by);
     launch_zgemm(a, nt, st);
     prof.end(st, pi);
 }
@@ -138,6 +138,11 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
 {
     std::vector<int> out;
     if (pd) pd->assign(sites.size(), 0);
+    struct ClsGuard {
+        int& c;
+        ClsGuard(int& x) : c(x) { c = 3; }
+        ~ClsGuard() { c = 1; }
+    } cls_guard(zgemm_cls);
     const int64_t nn = n * n;
     for (size_t b0 = 0; b0 < sites.size(); b0 += (size_t)NBLD) {
         const int nb = (int)std::min<size_t>((size_t)NBLD, sites.size() - b0);
@@ -252,6 +257,8 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
             slot_gam[s] = sqrt(std::max(g2[i], 0.0));
             slot_last[s] = ++slot_clock;
             stats.rebuilds++;
+            if (priv) stats.builds_private++;
+            else stats.builds_shared++;
         }
         HIPCHK(hipStreamSynchronize(st));
     }

@@ -47,20 +47,31 @@ __global__ void __launch_bounds__(NT) k_dense_gemm(DenseApplyArgs a, int64_t kch
     }
     const int mrow = lane & 15;     // row within a 16-row block (A operand) / column (B operand)
     const int kq = lane >> 4;       // k index within the 4-wide step
+    // software pipeline: the next K tile is loaded into registers while the
+    // matrix cores work on the current one from LDS
+    constexpr int AQ = BM * BK / NT, XQ = BK * BN / NT;
+    zd ra[AQ], rx[XQ];
+    auto gload = [&](int64_t kt) {
+        const int64_t gi = i0 + tid % BM;
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int64_t gk = kt + tid / BM + (NT / BM) * q;
+            ra[q] = (gi < a.m && gk < kend) ? a.A[gi + gk * a.lda] : zmake(0.0, 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < XQ; ++q) {
+            const int64_t gk = kt + tid / BN + (NT / BN) * q;
+            rx[q] = (xcol && gk < kend) ? xcol[gk] : zmake(0.0, 0.0);
+        }
+    };
+    if (kbeg < kend) gload(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-        // stage A[i0 : i0+64, k0 : k0+32] as As[k][i]
-        for (int e = tid; e < BM * BK; e += NT) {
-            int ii = e % BM, kk = e / BM;
-            int64_t gi = i0 + ii, gk = k0 + kk;
-            As[kk][ii] = (gi < a.m && gk < kend) ? a.A[gi + gk * a.lda] : zmake(0.0, 0.0);
-        }
-        // stage X[k0 : k0+32, j0 : j0+32] as Xs[k][j]
-        for (int kk = tid / BN; kk < BK; kk += NT / BN) {
-            int64_t gk = k0 + kk;
-            Xs[kk][jl] = (xcol && gk < kend) ? xcol[gk] : zmake(0.0, 0.0);
-        }
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) As[tid / BM + (NT / BM) * q][tid % BM] = ra[q];
+#pragma unroll
+        for (int q = 0; q < XQ; ++q) Xs[tid / BN + (NT / BN) * q][jl] = rx[q];
         __syncthreads();
-        // wave w: rows 16 w .. 16 w + 15 of the 64-row tile, columns 0..31 (2 blocks)
+        if (k0 + BK < kend) gload(k0 + BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             zd av = As[ks + kq][wave * 16 + mrow];
@@ -214,27 +225,45 @@ __global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
         acc_im[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
     }
     const int mrow = lane & 15, kq = lane >> 4;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    // software pipeline: the next K tile is loaded into registers while the
+    // matrix cores work on the current one from LDS
+    constexpr int AQ = BM * BK / NT;
+    zd ra[AQ], rb[BQ];
+    auto gload = [&](int64_t kt) {
         if (a.opA == 0) {
-            for (int e = tid; e < BM * BK; e += NT) {
-                int ii = e % BM, kk = e / BM;
-                int64_t gi = i0 + ii, gk = k0 + kk;
-                As[kk][ii] = (gi < a.M && gk < kend) ? A[gi + gk * a.lda] : zmake(0.0, 0.0);
+            const int64_t gi = i0 + tid % BM;
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) {
+                const int64_t gk = kt + tid / BM + (NT / BM) * q;
+                ra[q] = (gi < a.M && gk < kend) ? A[gi + gk * a.lda] : zmake(0.0, 0.0);
             }
         } else {
-            for (int e = tid; e < BM * BK; e += NT) {
-                int kk = e % BK, ii = e / BK;
-                int64_t gi = i0 + ii, gk = k0 + kk;
-                As[kk][ii] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
+            const int64_t gk = kt + tid % BK;
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) {
+                const int64_t gi = i0 + tid / BK + (NT / BK) * q;
+                ra[q] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
             }
         }
 #pragma unroll
         for (int q = 0; q < BQ; ++q) {
-            const int kk = tid % BK, jj = tid / BK + (NT / BK) * q;
-            const int64_t gk = k0 + kk;
-            Bs[kk][jj] = (bcol[q] && gk < kend) ? bcol[q][gk] : zmake(0.0, 0.0);
+            const int64_t gk = kt + tid % BK;
+            rb[q] = (bcol[q] && gk < kend) ? bcol[q][gk] : zmake(0.0, 0.0);
         }
+    };
+    if (kbeg < kend) gload(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        if (a.opA == 0) {
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) As[tid / BM + (NT / BM) * q][tid % BM] = ra[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) As[tid % BK][tid / BK + (NT / BK) * q] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) Bs[tid % BK][tid / BK + (NT / BK) * q] = rb[q];
         __syncthreads();
+        if (k0 + BK < kend) gload(k0 + BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             zd av = As[ks + kq][wave * 16 + mrow];

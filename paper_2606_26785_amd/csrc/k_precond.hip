@@ -109,10 +109,12 @@ void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n
 // read) redundantly in LDS and forms X = R_kk^{-1}; chunk 0 writes X into
 // Dinv and into the diagonal block of Finv (when non-null) and raises notpd
 // on a non-positive pivot; chunk c >= 1 turns columns
-// k1 + (c - 1) PANEL_W ... of the block row into the row panel of the factor,
+// k1 + (c - 1) PANEL_CHUNK ... of the block row (PANEL_W at a time) into the
+// row panel of the factor,
 // A[k, cols] <- X^* A[k, cols] (= R_kk^{-*} A[k, cols]).  Replaces a
 // single-workgroup diagonal kernel plus a separate panel product per step.
 #define PANEL_W 64
+#define PANEL_CHUNK 256
 __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_t strideA, int64_t n, int64_t k0,
                                                   int kb, zd* Dinv, int64_t strideD, zd* Finv, int64_t strideF,
                                                   double floor_piv, int* notpd)
@@ -126,8 +128,8 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
     const int chunk = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t k1 = k0 + kb;
-    const int64_t c0 = k1 + (int64_t)(chunk - 1) * PANEL_W;
-    if (chunk > 0 && c0 >= n) return;
+    const int64_t cbeg = k1 + (int64_t)(chunk - 1) * PANEL_CHUNK;
+    if (chunk > 0 && cbeg >= n) return;
     zd* Ab = A + (size_t)tile * strideA;
     if (tid == 0) bad = 0;
     for (int e = tid; e < kb * kb; e += NT) {
@@ -176,18 +178,22 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
         }
         return;
     }
-    const int w = (int)((n - c0) < PANEL_W ? (n - c0) : PANEL_W);
-    for (int e = tid; e < kb * PANEL_W; e += NT) {
-        int i = e % kb, c = e / kb;
-        Pn[i][c] = (c < w) ? Ab[k0 + i + (c0 + c) * n] : zmake(0.0, 0.0);
-    }
-    __syncthreads();
-    // out[i][c] = sum_{l <= i} conj(X[l][i]) Pn[l][c]
-    for (int e = tid; e < kb * w; e += NT) {
-        int i = e % kb, c = e / kb;
-        zd s = zmake(0.0, 0.0);
-        for (int l = 0; l <= i; ++l) s = zadd(s, zcmul(X[l][i], Pn[l][c]));
-        Ab[k0 + i + (c0 + c) * n] = s;
+    const int64_t cend = (cbeg + PANEL_CHUNK < n) ? cbeg + PANEL_CHUNK : n;
+    for (int64_t c0 = cbeg; c0 < cend; c0 += PANEL_W) {
+        const int w = (int)((cend - c0) < PANEL_W ? (cend - c0) : PANEL_W);
+        __syncthreads();
+        for (int e = tid; e < kb * PANEL_W; e += NT) {
+            int i = e % kb, c = e / kb;
+            Pn[i][c] = (c < w) ? Ab[k0 + i + (c0 + c) * n] : zmake(0.0, 0.0);
+        }
+        __syncthreads();
+        // out[i][c] = sum_{l <= i} conj(X[l][i]) Pn[l][c]
+        for (int e = tid; e < kb * w; e += NT) {
+            int i = e % kb, c = e / kb;
+            zd s = zmake(0.0, 0.0);
+            for (int l = 0; l <= i; ++l) s = zadd(s, zcmul(X[l][i], Pn[l][c]));
+            Ab[k0 + i + (c0 + c) * n] = s;
+        }
     }
 }
 
@@ -196,7 +202,7 @@ void launch_chol_step(const int* list, int nt, zd* A, int64_t strideA, int64_t n
 {
     if (nt <= 0) return;
     const int64_t rest = n - (k0 + kb);
-    const unsigned chunks = 1 + (unsigned)((rest + PANEL_W - 1) / PANEL_W);
+    const unsigned chunks = 1 + (unsigned)((rest + PANEL_CHUNK - 1) / PANEL_CHUNK);
     hipLaunchKernelGGL(k_chol_step, dim3(chunks, nt), dim3(NT), 0, s, list, A, strideA, n, k0, kb, Dinv, strideD,
                        Finv, strideF, floor_piv, notpd);
 }

@@ -43,7 +43,7 @@ void ps_default_params(ps_params* p)
     p->zdag_re = NAN;
     p->zdag_im = NAN;
     p->seed = 20261203ull;
-    p->eta_abs = 1e-9;
+    p->eta_abs = 8e-9;
     p->rho_small = 1e-5;
     p->profile = 0;
     p->verbose = 0;
