@@ -427,7 +427,9 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                         }
                         std::vector<char> drop(R.size(), 0);
                         for (size_t q = 0; q < ci.size(); ++q) {
-                            if (!pd[q]) continue;
+                            // a failed test ends the cluster regime of the tile
+                            // until one of its refinements is certified again
+                            if (!pd[q]) { cluster[R[ci[q]]] = 0; continue; }
                             const int i = ci[q], t = R[i], jb = Rsrc[i];
                             const int pt = tiles[t].order[tiles[t].cursor];
                             sig[pt] = h_xi_keep[jb];

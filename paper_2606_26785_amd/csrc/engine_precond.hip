@@ -53,7 +53,7 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
     double by = 16.0 * nt * ((double)M * Kd * (tri ? 0.5 : 1.0) + (double)Kd * N +
                              (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
     int pi = prof.begin(st, zgemm_cls, fl, by);
-    launch_zgemm(a, nt, st);
+    launch_zgemm(a, nt, st, zgemm_cls == 3 ? 1 : 0);
     prof.end(st, pi);
 }
 

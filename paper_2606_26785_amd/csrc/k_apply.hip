@@ -183,7 +183,7 @@ void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s)
 // computed (Hermitian rank-k updates).  The K loop of a workgroup finishes
 // before its epilogue writes, so C may alias B when M <= 64 (in-place
 // left-multiplication of a panel by a small matrix).
-__global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
+__device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
 {
     __shared__ zd As[BK][BM + 1];
     __shared__ zd Bs[BK][BN + 1];
@@ -301,6 +301,11 @@ __global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a)
     }
 }
 
+// two names for one kernel (k_zgemm: preconditioner applies; k_zgemm_fact:
+// products inside factorizations), so that profiles separate them
+__global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a) { k_zgemm_body(a); }
+__global__ void __launch_bounds__(NT) k_zgemm_fact(ZgemmArgs a) { k_zgemm_body(a); }
+
 // sum of the split-K partials into C (alpha, beta as in k_zgemm)
 __global__ void __launch_bounds__(NT) k_zgemm_reduce(ZgemmArgs a, int nb)
 {
@@ -324,12 +329,13 @@ __global__ void __launch_bounds__(NT) k_zgemm_reduce(ZgemmArgs a, int nb)
     *cp = val;
 }
 
-void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s)
+void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact)
 {
     if (nbatch <= 0 || a.M <= 0 || a.N <= 0) return;
     const int sk = a.splitk > 1 ? a.splitk : 1;
     dim3 g((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + BN - 1) / BN), nbatch * sk);
-    hipLaunchKernelGGL(k_zgemm, g, dim3(NT), 0, s, a);
+    if (fact) hipLaunchKernelGGL(k_zgemm_fact, g, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL(k_zgemm, g, dim3(NT), 0, s, a);
     if (sk > 1) {
         dim3 g2((unsigned)((a.M * a.N + NT - 1) / NT), nbatch);
         hipLaunchKernelGGL(k_zgemm_reduce, g2, dim3(NT), 0, s, a, nbatch);

@@ -122,7 +122,6 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
     __shared__ zd R[32][33];
     __shared__ zd X[32][33];
     __shared__ zd Pn[32][PANEL_W + 1];
-    __shared__ double piv;
     __shared__ int bad;
     const int tile = list[blockIdx.y];
     const int chunk = blockIdx.x;
@@ -137,37 +136,43 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
         R[i][j] = (i <= j) ? Ab[k0 + i + (k0 + j) * n] : zmake(0.0, 0.0);
     }
     __syncthreads();
-    for (int j = 0; j < kb; ++j) {
-        if (tid == 0) {
+    // right-looking factorization with one barrier per pivot: in phase j the
+    // trailing rows a > j are updated from the unscaled row j
+    // (R[a][c] -= conj(R[j][a]) R[j][c] / d_j), and row j - 1, which nothing
+    // reads any more, is scaled by 1 / sqrt(d_{j-1})
+    double pprev = 1.0;
+    for (int j = 0; j <= kb; ++j) {
+        double pj = 1.0, ipj2 = 1.0;
+        if (j < kb) {
             double d = R[j][j].x;
-            if (!(d > 0.0)) bad = 1;
+            if (!(d > 0.0) && tid == 0) bad = 1;
             if (!(d > floor_piv)) d = floor_piv;
-            piv = sqrt(d);
+            pj = sqrt(d);
+            ipj2 = 1.0 / d;
         }
-        __syncthreads();
-        const double p = piv;
-        for (int c = j + tid; c < kb; c += NT) R[j][c] = (c == j) ? zmake(p, 0.0) : zscale(R[j][c], 1.0 / p);
-        __syncthreads();
         for (int e = tid; e < kb * kb; e += NT) {
-            int a2 = e % kb, c = e / kb;
-            if (a2 > j && c >= a2) R[a2][c] = zsub(R[a2][c], zcmul(R[j][a2], R[j][c]));
+            const int a2 = e % kb, c = e / kb;
+            if (j < kb && a2 > j && c >= a2) R[a2][c] = zsub(R[a2][c], zscale(zcmul(R[j][a2], R[j][c]), ipj2));
+            if (j > 0 && a2 == j - 1 && c >= a2) R[a2][c] = (c == a2) ? zmake(pprev, 0.0) : zscale(R[a2][c], 1.0 / pprev);
         }
+        pprev = pj;
         __syncthreads();
     }
-    // X = R^{-1} (upper), one thread per column
-    for (int c = tid; c < kb; c += NT) {
-        for (int i = kb - 1; i >= 0; --i) {
-            if (i > c) { X[i][c] = zmake(0.0, 0.0); continue; }
-            zd s = zmake(i == c ? 1.0 : 0.0, 0.0);
-            for (int l = i + 1; l <= c; ++l) s = zsub(s, zmul(R[i][l], X[l][c]));
-            X[i][c] = zscale(s, 1.0 / R[i][i].x);
-        }
-    }
-    __syncthreads();
     if (chunk == 0) {
         if (tid == 0 && bad) notpd[tile] = 1;
         zd* Db = Dinv ? Dinv + (size_t)tile * strideD + k0 : nullptr;
         zd* Fb = Finv ? Finv + (size_t)tile * strideF + k0 + k0 * n : nullptr;
+        if (!Db && !Fb) return;
+        // X = R^{-1} (upper), one thread per column
+        for (int c = tid; c < kb; c += NT) {
+            for (int i = kb - 1; i >= 0; --i) {
+                if (i > c) { X[i][c] = zmake(0.0, 0.0); continue; }
+                zd s = zmake(i == c ? 1.0 : 0.0, 0.0);
+                for (int l = i + 1; l <= c; ++l) s = zsub(s, zmul(R[i][l], X[l][c]));
+                X[i][c] = zscale(s, 1.0 / R[i][i].x);
+            }
+        }
+        __syncthreads();
         // (R_kk is not written back: the other workgroups of this launch
         // read the unfactored block, and later steps need only X and the
         // row panels)
@@ -181,19 +186,26 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
     const int64_t cend = (cbeg + PANEL_CHUNK < n) ? cbeg + PANEL_CHUNK : n;
     for (int64_t c0 = cbeg; c0 < cend; c0 += PANEL_W) {
         const int w = (int)((cend - c0) < PANEL_W ? (cend - c0) : PANEL_W);
-        __syncthreads();
         for (int e = tid; e < kb * PANEL_W; e += NT) {
             int i = e % kb, c = e / kb;
             Pn[i][c] = (c < w) ? Ab[k0 + i + (c0 + c) * n] : zmake(0.0, 0.0);
         }
         __syncthreads();
-        // out[i][c] = sum_{l <= i} conj(X[l][i]) Pn[l][c]
+        // R_kk^* Y = A[k, cols]: forward substitution, one thread per column
+        if (tid < w) {
+            const int c = tid;
+            for (int i = 0; i < kb; ++i) {
+                zd sacc = Pn[i][c];
+                for (int l = 0; l < i; ++l) sacc = zsub(sacc, zcmul(R[l][i], Pn[l][c]));
+                Pn[i][c] = zscale(sacc, 1.0 / R[i][i].x);
+            }
+        }
+        __syncthreads();
         for (int e = tid; e < kb * w; e += NT) {
             int i = e % kb, c = e / kb;
-            zd s = zmake(0.0, 0.0);
-            for (int l = 0; l <= i; ++l) s = zadd(s, zcmul(X[l][i], Pn[l][c]));
-            Ab[k0 + i + (c0 + c) * n] = s;
+            Ab[k0 + i + (c0 + c) * n] = Pn[i][c];
         }
+        __syncthreads();
     }
 }
 

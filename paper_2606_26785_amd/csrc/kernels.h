@@ -190,7 +190,7 @@ struct ZgemmArgs {
     // are one wide product; N is the largest gcnt[b] * cw
     const int* gtile; const int* goff; const int* gcnt; int cw;
 };
-void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s);
+void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact = 0);
 
 // dense base preconditioner (k_precond.hip)
 #define PRE_NB 32

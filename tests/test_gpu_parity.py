@@ -8,6 +8,8 @@ below only through the orthonormality error of the basis, so
 sigma_gpu >= sigma_ref - 1e-9 ||C||_2 (misconvergence to a larger singular
 value shows up in the first bound instead).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -153,3 +155,33 @@ def test_dense_base_preconditioner(n, m):
     g_ref = 1.0 / np.linalg.svd(A, compute_uv=False)[-1]
     assert abs(gamma - g_ref) <= 1e-6 * g_ref
     mat.close()
+
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "toeplitz_n4000_grid200_sigma.npy")
+
+
+@pytest.mark.parametrize("i0,j0", [(184, 0), (136, 136)])
+def test_toeplitz_full_size_windows(i0, j0):
+    """The n = 4000 dense Toeplitz matrix of the benchmark on 16 x 16 blocks of
+    its full 200 x 200 grid, against the oracle values stored for those grid
+    points (tests/golden, written by make_toeplitz_ref.py from the banded
+    oracle): the far exterior corner, where the smallest singular values form
+    a tight cluster, and a block across the boundary of the spectrum (noise
+    level, boundary band and exterior points)."""
+    if not os.path.exists(GOLD):
+        pytest.skip("oracle reference not generated")
+    gold = np.load(GOLD).reshape(200, 200)
+    wl = workloads.toeplitz_band()
+    re_lo, re_hi, im_lo, im_hi = wl.region
+    w = 16
+    xs = [re_lo + (re_hi - re_lo) * i / 199 for i in (i0, i0 + w - 1)]
+    ys = [im_lo + (im_hi - im_lo) * j / 199 for j in (j0, j0 + w - 1)]
+    mat = P.create_from_workload(wl)
+    g = P.ps_grid(xs[0], xs[1], ys[0], ys[1], w, w)
+    res = P.ps_eval(mat, g, wl.eps)
+    normC = mat.norm_estimate / 1.01
+    mat.close()
+    ref = gold[j0:j0 + w, i0:i0 + w].reshape(-1)
+    sub = workloads.Workload(name="window", m=wl.m, n=wl.n, kind="dense", region=(xs[0], xs[1], ys[0], ys[1]),
+                             nx=w, ny=w, eps=wl.eps)
+    _check_parity(sub, res, ref, normC, "toeplitz n=4000 window (%d,%d)" % (i0, j0))
