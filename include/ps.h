@@ -120,6 +120,11 @@ typedef struct {
                            inertia test above, a shifted preconditioner
                            N(z) - (xi - 64 tau)^2 I, or an exact site at z
                            (default 30; 0 disables) */
+    int32_t cert_recycled; /* 1: in a cluster regime, test a recycled Ritz
+                           value that failed eq. (tolC) with the inertia test
+                           before starting LOBPCG (default 0: on the dense
+                           Toeplitz workload half of those tests fail and the
+                           sweep is 27% slower) */
     int32_t lipschitz;  /* 1 (default): after the sweep, points whose value
                            exceeds an upper bound from a finished grid
                            neighbour (the norm of C(z) on the neighbour's

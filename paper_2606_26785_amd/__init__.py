@@ -47,7 +47,7 @@ class ps_params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("eta_abs", ctypes.c_double), ("rho_small", ctypes.c_double),
                 ("profile", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("tol_abs", ctypes.c_double), ("esc_iters", ctypes.c_int32),
-                ("lipschitz", ctypes.c_int32)]
+                ("cert_recycled", ctypes.c_int32), ("lipschitz", ctypes.c_int32)]
 
 
 class ps_stats(ctypes.Structure):

@@ -383,7 +383,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 // in a cluster regime, where the recycled Ritz value is often
                 // already within tau although its residual fails eq. (tolC):
                 // test it directly before starting LOBPCG
-                if (use_prec && tau_c > 0.0 && P.esc_iters > 0) {
+                if (use_prec && tau_c > 0.0 && P.esc_iters > 0 && P.cert_recycled) {
                     std::vector<int> ci;
                     for (size_t i = 0; i < R.size(); ++i) {
                         const int t = R[i], jb = Rsrc[i];

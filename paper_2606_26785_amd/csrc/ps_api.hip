@@ -49,6 +49,7 @@ void ps_default_params(ps_params* p)
     p->verbose = 0;
     p->tol_abs = 8e-9;
     p->esc_iters = 30;
+    p->cert_recycled = 0;
     p->lipschitz = 1;
 }
 
