@@ -174,7 +174,7 @@ struct Engine {
     HBuf<int> h_notpd;
     std::vector<int> tile_slot;      // per tile: site of the running refinement (-1: K = I)
     std::vector<char> usek;          // per tile: this refinement uses the base preconditioner
-    DBuf<int> d_listK, d_listI, d_gmap;
+    DBuf<int> d_listI, d_gmap;
     HBuf<int> h_gmap;
     bool use_prec = false;
     void reset_slots();

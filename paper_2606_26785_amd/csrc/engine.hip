@@ -534,7 +534,7 @@ void Engine::size_for(int tiles)
     slot_valid.assign(NS, 0);
     slot_priv.assign(NS, 0);
     tile_slot.assign(t, -1);
-    d_listK.alloc(t); d_listI.alloc(t);
+    d_listI.alloc(t);
     usek.assign(t, 1);
     h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r)); h_nrm2.alloc(std::max<size_t>(t, NBLD) * 3 * r);
     h_small.alloc(std::max<size_t>(t, NBLD) * 4 + 8); h_C.alloc(t * K * r + 8); h_list.alloc(t + 1); h_z.alloc(t + J);

@@ -220,7 +220,6 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     const double nC = op.normC;
     bool any_uncert = false;
     const int64_t sS = (int64_t)n * 3 * r;
-    uint64_t round_seed = P.seed;
     std::vector<double> h_xi_keep;
     double t_ritz = 0, t_lob = 0, t_upd = 0;
     auto now = [] { return std::chrono::steady_clock::now(); };

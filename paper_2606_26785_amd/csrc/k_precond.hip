@@ -1,15 +1,16 @@
-// Dense base preconditioner K = F^* F ~ N(z_dag) = (C - z_dag S)^* (C - z_dag S)
-// (Sec. 3, eq. (twolevel) and the reconstruction rule of Sec. 3.3): F is the
-// upper Cholesky factor of N(z_dag) + delta I, computed by a right-looking
-// blocked Cholesky whose trailing updates run on the matrix cores (k_zgemm),
-// and F^{-1} is formed block column by block column alongside it, so that
-// K^{-1} W = F^{-1} (F^{-*} W) is two matrix-core products.
+// Kernels of the factorizations of N(z) - mu I, N(z) = (C - z S)^* (C - z S):
+// the dense base preconditioner K = F^* F ~ N(z_dag) (Sec. 3, eq. (twolevel)
+// and the reconstruction rule of Sec. 3.3), F the upper Cholesky factor of
+// N(z_dag) + delta I, and the inertia tests (N(z) - mu I positive definite).
+// The blocked Cholesky around them (engine_precond.hip) runs its trailing
+// updates and the columns of F^{-1} on the matrix cores (k_zgemm_fact), so
+// that K^{-1} W = F^{-1} (F^{-*} W) is two matrix-core products.
 #include "zdev.h"
 #include "kernels.h"
 
 #define NT 256
 
-// N = C^*C - conj(z) S^*C - z C^*S + (|z|^2 + shift) I for each tile in list
+// N = C^*C - conj(z) S^*C - z C^*S + (|z|^2 + shift) I for each matrix in list
 __global__ void k_form_normal(const int* list, const zd* CtC, const zd* C, int64_t ldc, const zd* CH, int64_t n,
                               const zd* zdag, const double* shift, zd* N, int64_t strideN)
 {
@@ -33,75 +34,6 @@ void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int
     if (nt <= 0) return;
     dim3 g((unsigned)((n * n + NT - 1) / NT), nt);
     hipLaunchKernelGGL(k_form_normal, g, dim3(NT), 0, s, list, CtC, C, ldc, CH, n, zdag, shift, N, strideN);
-}
-
-// Diagonal block (kb <= 32) of the blocked Cholesky: R_kk with R_kk^* R_kk = A_kk
-// (upper triangle of A_kk read), written back into A; its inverse written to
-// Dinv (rows k0.., ld n) and to the diagonal block of Finv (zeros below the
-// diagonal).  A pivot that is not positive sets notpd[tile] (the matrix is not
-// numerically positive definite); pivots are then floored at `floor_piv` so
-// that the factor stays finite.
-__global__ void __launch_bounds__(NT) k_chol_diag(const int* list, zd* A, int64_t strideA, int64_t n, int64_t k0,
-                                                  int kb, zd* Dinv, int64_t strideD, zd* Finv, int64_t strideF,
-                                                  double floor_piv, int* notpd)
-{
-    __shared__ zd R[32][33];
-    __shared__ zd X[32][33];
-    __shared__ double piv;
-    const int tile = list[blockIdx.x];
-    const int tid = threadIdx.x;
-    zd* Ab = A + (size_t)tile * strideA + k0 + k0 * n;
-    for (int e = tid; e < kb * kb; e += NT) {
-        int i = e % kb, j = e / kb;
-        R[i][j] = (i <= j) ? Ab[i + (int64_t)j * n] : zmake(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int j = 0; j < kb; ++j) {
-        if (tid == 0) {
-            double d = R[j][j].x;
-            if (!(d > 0.0)) notpd[tile] = 1;
-            if (!(d > floor_piv)) d = floor_piv;
-            piv = sqrt(d);
-        }
-        __syncthreads();
-        const double p = piv;
-        // row j of R: R[j][c] = A[j][c] / p for c >= j
-        for (int c = j + tid; c < kb; c += NT) R[j][c] = (c == j) ? zmake(p, 0.0) : zscale(R[j][c], 1.0 / p);
-        __syncthreads();
-        // trailing: A[a][c] -= conj(R[j][a]) R[j][c], j < a <= c
-        for (int e = tid; e < kb * kb; e += NT) {
-            int a2 = e % kb, c = e / kb;
-            if (a2 > j && c >= a2) R[a2][c] = zsub(R[a2][c], zcmul(R[j][a2], R[j][c]));
-        }
-        __syncthreads();
-    }
-    // X = R^{-1} (upper): column c by back substitution, one thread per column
-    for (int c = tid; c < kb; c += NT) {
-        for (int i = kb - 1; i >= 0; --i) {
-            if (i > c) { X[i][c] = zmake(0.0, 0.0); continue; }
-            zd s = zmake(i == c ? 1.0 : 0.0, 0.0);
-            for (int l = i + 1; l <= c; ++l) s = zsub(s, zmul(R[i][l], X[l][c]));
-            double rii = R[i][i].x;
-            X[i][c] = zscale(s, 1.0 / rii);
-        }
-    }
-    __syncthreads();
-    zd* Db = Dinv + (size_t)tile * strideD + k0;
-    zd* Fb = Finv + (size_t)tile * strideF + k0 + k0 * n;
-    for (int e = tid; e < kb * kb; e += NT) {
-        int i = e % kb, j = e / kb;
-        Ab[i + (int64_t)j * n] = (i <= j) ? R[i][j] : zmake(0.0, 0.0);
-        Db[i + (int64_t)j * n] = X[i][j];
-        Fb[i + (int64_t)j * n] = X[i][j];
-    }
-}
-
-void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
-                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s)
-{
-    if (nt <= 0) return;
-    hipLaunchKernelGGL(k_chol_diag, dim3(nt), dim3(NT), 0, s, list, A, strideA, n, k0, kb, Dinv, strideD, Finv,
-                       strideF, floor_piv, notpd);
 }
 
 // One step of the blocked Cholesky, fused: every workgroup of the grid
@@ -217,32 +149,6 @@ void launch_chol_step(const int* list, int nt, zd* A, int64_t strideA, int64_t n
     const unsigned chunks = 1 + (unsigned)((rest + PANEL_CHUNK - 1) / PANEL_CHUNK);
     hipLaunchKernelGGL(k_chol_step, dim3(chunks, nt), dim3(NT), 0, s, list, A, strideA, n, k0, kb, Dinv, strideD,
                        Finv, strideF, floor_piv, notpd);
-}
-
-// batched conjugate transpose of square n x n matrices (per tile)
-__global__ void k_conj_transpose_b(const int* list, const zd* A, int64_t stride, int64_t n, zd* B)
-{
-    __shared__ zd t[32][33];
-    const int tile = list[blockIdx.z];
-    const zd* Ab = A + (size_t)tile * stride;
-    zd* Bb = B + (size_t)tile * stride;
-    int64_t bi = (int64_t)blockIdx.x * 32, bj = (int64_t)blockIdx.y * 32;
-    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
-        int64_t i = bi + threadIdx.x, j = bj + k;
-        if (i < n && j < n) t[k][threadIdx.x] = Ab[i + j * n];
-    }
-    __syncthreads();
-    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
-        int64_t j = bj + threadIdx.x, i = bi + k;
-        if (i < n && j < n) Bb[j + i * n] = zconj(t[threadIdx.x][k]);
-    }
-}
-
-void launch_conj_transpose_b(const int* list, int nt, const zd* A, int64_t stride, int64_t n, zd* B, hipStream_t s)
-{
-    if (nt <= 0) return;
-    dim3 g((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32), nt);
-    hipLaunchKernelGGL(k_conj_transpose_b, g, dim3(32, 8), 0, s, list, A, stride, n, B);
 }
 
 __global__ void k_zero_tiles(const int* list, zd* A, int64_t stride, int64_t count)

@@ -282,27 +282,6 @@ void launch_scale_cols(const int* list, int ntiles, zd* A, int64_t stride, int64
     hipLaunchKernelGGL(k_scale_cols, g, dim3(NT), 0, s, list, A, stride, lda, rows, cols, d, ldd, invert);
 }
 
-__global__ void k_zaxpy_tile(const int* list, const zd* z, int conjz, zd* Y, int64_t ystride, int64_t ldy,
-                             const zd* X, int64_t xstride, int64_t ldx, int64_t rows, int cols)
-{
-    const int tile = list[blockIdx.y];
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= rows * cols) return;
-    int64_t i = e % rows, j = e / rows;
-    zd zz = z[tile];
-    if (conjz) zz.y = -zz.y;
-    zd* y = Y + (size_t)tile * ystride + i + j * ldy;
-    zd x = X[(size_t)tile * xstride + i + j * ldx];
-    *y = zsub(*y, zmul(zz, x));
-}
-void launch_zaxpy_tile(const int* list, int ntiles, const zd* z, int conjz, zd* Y, int64_t ystride, int64_t ldy,
-                       const zd* X, int64_t xstride, int64_t ldx, int64_t rows, int cols, hipStream_t s)
-{
-    if (ntiles <= 0 || rows * cols == 0) return;
-    dim3 g((unsigned)((rows * cols + NT - 1) / NT), ntiles);
-    hipLaunchKernelGGL(k_zaxpy_tile, g, dim3(NT), 0, s, list, z, conjz, Y, ystride, ldy, X, xstride, ldx, rows, cols);
-}
-
 __global__ void k_resid_xi(const int* list, zd* Y, int64_t ystride, int64_t ldy, const zd* X, int64_t xstride,
                            int64_t ldx, const double* xi, int ldxi, int64_t rows, int cols)
 {

@@ -128,9 +128,6 @@ void launch_scale_cols(const int* list, int ntiles, zd* A, int64_t stride, int64
                        int cols, const double* d, int ldd, int invert, hipStream_t s);
 // W = Y - conj(z) X[:n] padded: used for C(z)^* Y = C^* Y - conj(z) S^* Y and
 // C(z) X = C X - z S X.  mode 0: Y[:n] -= zc * X[:n]; rows beyond n untouched.
-void launch_zaxpy_tile(const int* list, int ntiles, const zd* z, int conjz, zd* Y, int64_t ystride,
-                       int64_t ldy, const zd* X, int64_t xstride, int64_t ldx, int64_t rows, int cols,
-                       hipStream_t s);
 // R = Y - X diag(xi^2)
 void launch_tile_dot0(const int* list, int ntiles, const zd* X, int64_t xs, const zd* Y, int64_t ys, int64_t n,
                       zd* out, hipStream_t s);
@@ -197,9 +194,6 @@ void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact = 0);
 #define PRE_OB 128
 void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int64_t ldc, const zd* CH,
                         int64_t n, const zd* zdag, const double* shift, zd* N, int64_t strideN, hipStream_t s);
-void launch_chol_diag(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
-                      int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s);
 void launch_chol_step(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
                       int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s);
-void launch_conj_transpose_b(const int* list, int nt, const zd* A, int64_t stride, int64_t n, zd* B, hipStream_t s);
 void launch_zero_tiles(const int* list, int nt, zd* A, int64_t stride, int64_t count, hipStream_t s);
