@@ -78,8 +78,11 @@ typedef struct {
 typedef struct {
     int32_t r;          /* singular LOBPCG block size r (default 8) */
     int32_t k_max;      /* cap on the recycled singular dimension p r (default 32) */
-    int32_t rbar;       /* projection block size rbar (default 16) */
-    int32_t kbar_max;   /* cap on the recycled projection dimension (default 64) */
+    int32_t rbar;       /* projection block size rbar (default 16; the
+                           projection subspace of Sec. 3.2 is not built in
+                           this version: validated, otherwise unused) */
+    int32_t kbar_max;   /* cap on the recycled projection dimension (default
+                           64; validated, otherwise unused) */
     int32_t max_iters;  /* LOBPCG iteration cap (default 300) */
     int32_t precond;    /* LOBPCG preconditioner K (Sec. 3): 0: K = I;
                            1: base preconditioner K = F^* F ~ N(z_dag), rebuilt
@@ -93,9 +96,11 @@ typedef struct {
                            seeded random start (the comparison solver) */
     double eta;         /* acceptance tolerance of eq. (tolC) (default 1e-6) */
     double eta_svd;     /* LOBPCG convergence tolerance, eq. (tolSVD) (1e-9) */
-    double eta_proj;    /* projection test tolerance, eq. (tolTz) (1e-4) */
+    double eta_proj;    /* projection test tolerance, eq. (tolTz) (1e-4;
+                           unused in this version) */
     double omega;       /* pruning threshold of eq. (omegaCond) (1.6) */
-    double tau_min;     /* eq. (tauRecycle) lower threshold (1e-3) */
+    double tau_min;     /* eq. (tauRecycle) lower threshold (1e-3; it bounds
+                           the projection part, unused in this version) */
     double tau_max;     /* eq. (tauRecycle) upper threshold (30) */
     double zdag_re;     /* first base-preconditioner site; NaN = region centre */
     double zdag_im;

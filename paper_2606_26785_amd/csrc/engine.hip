@@ -515,10 +515,10 @@ void Engine::size_for(int tiles)
     NS = 0;
     if (use_prec) {
         const size_t nn = (size_t)n * n;
-        // staging for up to 16 simultaneous constructions; the site pool holds
+        // staging for up to 32 simultaneous constructions; the site pool holds
         // one slot per tile plus the staging count (so a free slot always
         // exists), within 96 GB
-        NBLD = 16;
+        NBLD = 32;
         const size_t cap = std::max<size_t>(2, ((size_t)96 << 30) / (nn * sizeof(zd)));
         NS = (int)std::min<size_t>(t + NBLD, cap);
         PN.alloc(NBLD * nn); Fb.alloc(NBLD * nn); Finv.alloc((size_t)NS * nn);

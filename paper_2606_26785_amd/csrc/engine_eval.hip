@@ -648,7 +648,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     if (!isfin[t]) certified[t] = 1;
                 }
             // inertia tests wait (while their refinements keep iterating) until
-            // a full batch is pending, the oldest has waited 4 steps, or
+            // a full batch is pending, the oldest has waited 10 steps, or
             // nothing else is running
             {
                 std::vector<int> still;
@@ -659,7 +659,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 int nrun = 0;
                 for (int t : run) nrun += !isfin[t];
                 bool flush = (int)pending.size() >= NBLD || (int)pending.size() >= nrun;
-                for (int t : pending) flush |= loops - cert_since[t] >= 6;
+                for (int t : pending) flush |= loops - cert_since[t] >= 10;
                 if (flush && !pending.empty()) {
                     std::vector<zd> cs;
                     std::vector<double> cm;
