@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--save-sigma", default="", help="write the grid's sigma and flags to this .npy")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path shards by grid tile; see DESIGN.md)",
+        print("bench.py: measures one GPU only (the path would shard by grid tile, one band of tiles per GPU)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -111,7 +111,7 @@ struct Engine {
     // ---- per-eval sizing
     int T = 0;         // tile slots
     int r = 8, K = 32; // block size, recycled cap
-    int B = 20;        // ritz window per round
+    int B = 20;        // points per Ritz test window of a tile
     int64_t n = 0, m = 0;
 
     // singular store (primary + update scratch)

@@ -423,7 +423,7 @@ void Engine::create(const ps_matrix_desc* d, const ps_params* p, hipStream_t s)
     K = P.k_max;
     if (P.precond < 0) P.precond = (op.kind == PS_DENSE) ? 1 : 0;
     if (P.precond > 0 && op.kind != PS_DENSE)
-        throw InvalidArg("precond = 1 needs a dense matrix in this build");
+        throw InvalidArg("precond = 1 needs a dense matrix in this version");
     use_prec = P.precond > 0;
     size_for(1);
     estimate_norm();

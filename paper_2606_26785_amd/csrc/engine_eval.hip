@@ -158,10 +158,12 @@ void Engine::update_store(const std::vector<int>& Lin)
 // alternating directions, a snake inside each column batch) and runs the
 // sequential algorithm with its own recycled store, so that every point is
 // tested against the store as updated by all refinements before it in its
-// tile.  One round evaluates the next b points of every tile against its
-// store in one batched launch, accepts the leading run of points that pass,
-// and refines the first rejected point of every tile in one batched
-// LOBPCG-SVD, followed by the batched store updates.
+// tile.  Tiles are scheduled by continuous batching: an idle tile tests its
+// next b points against its store (one batched launch for all idle tiles),
+// accepts the leading run of points that pass and starts LOBPCG-SVD on the
+// first rejected one; every scheduler step advances all running refinements
+// by one iteration, and a tile whose refinement ends updates its store and
+// becomes idle again.
 static void tile_orders(int nx, int ny, int tx, int ty, int b, std::vector<Tile>& tiles)
 {
     tiles.clear();

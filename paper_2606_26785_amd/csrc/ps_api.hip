@@ -95,7 +95,7 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
         return fail(PS_EINVAL, "bad tolerances");
     if (p.precond > 1 || p.precond < -1) return fail(PS_EINVAL, "precond must be -1, 0 or 1");
     if (p.precond == 1 && d->kind != PS_DENSE)
-        return fail(PS_EUNSUPPORTED, "the base preconditioner needs a dense matrix in this build");
+        return fail(PS_EUNSUPPORTED, "the base preconditioner needs a dense matrix in this version");
     if (d->kind == PS_DENSE && !d->on_device) {
         for (int64_t j = 0; j < d->n; ++j)
             for (int64_t i = 0; i < 2 * d->m; ++i)

@@ -90,3 +90,28 @@ def test_inertia_test_brackets_sigma_min():
         except np.linalg.LinAlgError:
             ok = False
         assert ok == expect, (f, ok)
+
+
+def test_two_level_preconditioner_lifts_smallest_pencil_eigenvalues():
+    """Lemma 3.1 (Sec. 3.1): with E the K-orthonormal eigenvectors of the
+    rbar smallest eigenvalues of the pencil (N, K), K_E^{-1} = K^{-1} +
+    E Lambda^{-1} E^* (eq. (twolevel) with Z = E, since Z^* N Z = Lambda)
+    maps them to lambda_j + 1 and leaves the others.  The coarse part of the
+    preconditioner is not built in this version; this pins the reading of
+    Z^* N(z) Z it relies on."""
+    rng = np.random.default_rng(11)
+    n, rbar = 24, 4
+    A = _cn(rng, n, n)
+    N = A.conj().T @ A + 1e-3 * np.eye(n)
+    B = _cn(rng, n, n)
+    K = B.conj().T @ B + n * np.eye(n)
+    Fc = np.linalg.cholesky(K).conj().T                 # K = F^* F
+    Fi = np.linalg.inv(Fc)
+    lam, Xb = np.linalg.eigh(Fi.conj().T @ N @ Fi)      # F^{-*} N F^{-1} Xbar = Xbar Lambda
+    E = Fi @ Xb[:, :rbar]                               # E = F^{-1} Xbar, K-orthonormal
+    assert np.allclose(E.conj().T @ K @ E, np.eye(rbar), atol=1e-10)
+    assert np.allclose(E.conj().T @ N @ E, np.diag(lam[:rbar]), atol=1e-8)
+    KEinv = np.linalg.inv(K) + E @ np.diag(1.0 / lam[:rbar]) @ E.conj().T
+    got = np.sort(np.linalg.eigvals(KEinv @ N).real)
+    want = np.sort(np.concatenate([lam[:rbar] + 1.0, lam[rbar:]]))
+    assert np.allclose(got, want, rtol=1e-8, atol=1e-8)
