@@ -37,7 +37,8 @@ def main():
     ap.add_argument("--cpu-points", type=int, default=16, help="grid points in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--verbose", action="store_true", help="progress lines on stderr (the default)")
+    ap.add_argument("--quiet", action="store_true", help="no progress lines")
     ap.add_argument("--tiles-x", type=int, default=0)
     ap.add_argument("--tiles-y", type=int, default=0)
     ap.add_argument("--batch", type=int, default=20)
@@ -48,17 +49,20 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    log("loading torch and the library")
     import numpy as np
     import torch
     import paper_2606_26785_amd as P
     import workloads
 
-    def log(msg):
-        print("[bench] " + msg, file=sys.stderr, flush=True)
-
     wl = workloads.toeplitz_band(n=args.n, grid=args.grid)
     npts = wl.npts
-    params = P.default_params(profile=1, verbose=1 if args.verbose else 0, tiles_x=args.tiles_x,
+    # progress lines go to stderr every few seconds: a sweep of the full grid
+    # takes minutes, and the one JSON line stays alone on stdout
+    params = P.default_params(profile=1, verbose=0 if args.quiet else 1, tiles_x=args.tiles_x,
                               tiles_y=args.tiles_y, batch=args.batch)
     t0 = time.perf_counter()
     mat = P.create_from_workload(wl, params=params)
