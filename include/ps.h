@@ -60,6 +60,9 @@ typedef enum {
 
 typedef enum { PS_DENSE = 0, PS_CSR = 1 } ps_kind;
 
+/* Number of event-timed kernel classes in ps_stats. */
+#define PS_NCLASS 8
+
 /* Input matrix C (m x n, m >= n >= 1). */
 typedef struct {
     int32_t kind;           /* PS_DENSE or PS_CSR */
@@ -91,6 +94,9 @@ typedef struct {
                            -1 (default): 1 for dense C, 0 for CSR */
     int32_t tiles_x;    /* grid-front partition: tiles along x (0 = auto) */
     int32_t tiles_y;    /* tiles along y (0 = auto) */
+    int32_t tile_points;/* auto partition: points per tile (default 20) */
+    int32_t tile_mem_gb;/* auto partition: device memory for per-tile state
+                           (default 48) */
     int32_t batch;      /* b of the batch-zigzag traversal (default 20) */
     int32_t recycle;    /* 1: recycled path; 0: plain per-point LOBPCG from a
                            seeded random start (the comparison solver) */
@@ -157,18 +163,27 @@ typedef struct {
     int64_t cert_tests;    /* inertia tests (Cholesky of N(z) - mu I) run */
     int64_t builds_shared; /* preconditioner sites built for sharing (rebuild rule) */
     int64_t builds_private;/* sites built for one slow refinement (shifted or exact) */
+    int64_t ritz_jobs;     /* Ritz extractions from a recycled store (points tested) */
+    int64_t store_updates; /* updateRecy calls that appended a block (Alg. 2) */
+    int64_t precond_iters; /* LOBPCG iterations that applied K^{-1} != I */
+    int64_t repairs;       /* LOBPCG steps whose search space lost rank and was rebuilt */
     double t_total_ms;     /* wall time of ps_eval */
     double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
-    /* with profile = 1: event-timed kernel classes (launches, device ms,
-     * algorithmic flops and bytes).  Class 0: operator applies C X, C^* Y
-     * (dense: matrix-core GEMM + split-K reduction; CSR: SpMM); class 1:
-     * preconditioner applies K^{-1} W; class 2: Ritz extraction (per-point
-     * Jacobi SVD + residual); class 3: matrix-core products of the
-     * factorizations (preconditioner sites and inertia tests). */
-    int64_t k_launches[4];
-    double k_ms[4];
-    double k_flops[4];
-    double k_bytes[4];
+    /* with profile >= 1: event-timed kernel classes (launches, device ms,
+     * algorithmic flops and bytes per class).  Class 0: operator applies
+     * C X, C^* Y (dense: matrix-core GEMM + split-K reduction; CSR: SpMM);
+     * class 1: preconditioner applies K^{-1} W; class 2: Ritz extraction
+     * (per-point QR + Jacobi SVD + residual); class 3: matrix-core products
+     * inside factorizations (preconditioner sites, inertia tests); class 4:
+     * the diagonal-block steps of those factorizations and the forming of
+     * N(z).  With profile >= 2 also class 5: per-tile small dense kernels
+     * (Rayleigh-Ritz-SVD, Cholesky of Gram matrices, SVQB, rotations);
+     * class 6: tall-skinny Gram, product and norm kernels; class 7: the
+     * rest (copies, fills). */
+    int64_t k_launches[PS_NCLASS];
+    double k_ms[PS_NCLASS];
+    double k_flops[PS_NCLASS];
+    double k_bytes[PS_NCLASS];
 } ps_stats;
 
 /* Per-point flag bits written to `flags`. */

@@ -28,6 +28,9 @@ FLAG_REFINED = 2
 FLAG_UNCERTIFIED = 4
 FLAG_PROJ_REFINED = 8
 FLAG_REBUILD = 16
+FLAG_CERTIFIED = 32
+FLAG_LIPSCHITZ = 64
+NCLASS = 8          # PS_NCLASS: event-timed kernel classes in ps_stats
 
 
 class ps_matrix_desc(ctypes.Structure):
@@ -40,7 +43,8 @@ class ps_matrix_desc(ctypes.Structure):
 class ps_params(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("k_max", ctypes.c_int32), ("rbar", ctypes.c_int32),
                 ("kbar_max", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32), ("tile_points", ctypes.c_int32),
+                ("tile_mem_gb", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("recycle", ctypes.c_int32), ("eta", ctypes.c_double), ("eta_svd", ctypes.c_double),
                 ("eta_proj", ctypes.c_double), ("omega", ctypes.c_double), ("tau_min", ctypes.c_double),
                 ("tau_max", ctypes.c_double), ("zdag_re", ctypes.c_double), ("zdag_im", ctypes.c_double),
@@ -53,11 +57,13 @@ class ps_params(ctypes.Structure):
 class ps_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "points", "accepted", "refined", "uncertified", "lobpcg_iters", "proj_accepted",
-        "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds", "certified", "lipschitz_redo", "guard_rejects", "cert_tests", "builds_shared", "builds_private")] + \
+        "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds", "certified", "lipschitz_redo",
+        "guard_rejects", "cert_tests", "builds_shared", "builds_private", "ritz_jobs", "store_updates",
+        "precond_iters", "repairs")] + \
         [(n, ctypes.c_double) for n in ("t_total_ms", "t_ritz_ms", "t_lobpcg_ms", "t_update_ms",
                                         "t_precond_ms")] + \
-        [("k_launches", ctypes.c_int64 * 4), ("k_ms", ctypes.c_double * 4), ("k_flops", ctypes.c_double * 4),
-         ("k_bytes", ctypes.c_double * 4)]
+        [("k_launches", ctypes.c_int64 * NCLASS), ("k_ms", ctypes.c_double * NCLASS),
+         ("k_flops", ctypes.c_double * NCLASS), ("k_bytes", ctypes.c_double * NCLASS)]
 
     def as_dict(self):
         out = {}

@@ -97,6 +97,7 @@ struct KProf {
     std::vector<double> flops, bytes;
     size_t used = 0;
     bool on = false;
+    int level = 0;    // 1: classes 0-4; 2: every class
     int begin(hipStream_t s, int c, double fl, double by);
     void end(hipStream_t s, int idx);
     void collect(ps_stats& st);
@@ -208,6 +209,13 @@ struct Engine {
     void apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xstride, int64_t ldx, zd* Y,
                int64_t ystride, int64_t ldy, int w, const zd* dz);
 
+    // pinned staging ring for host-to-device uploads: every upload copies its
+    // bytes into a fresh slice, so an upload never waits for the stream (the
+    // stream is drained only when the ring wraps around)
+    HBuf<char> ring;
+    size_t ring_pos = 0;
+    void h2d(void* dst, const void* src, size_t bytes);
+
     // ---- building blocks
     void upload_list(const std::vector<int>& L, DBuf<int>& dst);
     void gram(const int* dlist, int nt, const BlockList& A, const BlockList& Bl, int camax, int cbmax, void* out,
@@ -218,8 +226,9 @@ struct Engine {
     void colnorm2(const int* dlist, int nt, const BlockList& A, int camax, double* out, int ldo);
     void orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, int64_t wstride, int64_t ldw,
                         int64_t rows, int cols, const BlockList* against, int against_max, uint64_t seed);
+    // nzero (optional, per tile): number of pivots the Cholesky treated as zero
     void r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul, int cfixed,
-                  zd* R, int64_t strideR, int ldR);
+                  zd* R, int64_t strideR, int ldR, int* nzero = nullptr);
 
     // ---- algorithm steps
     // LOBPCG-SVD as a per-tile state machine: lob_start runs the first
@@ -232,9 +241,13 @@ struct Engine {
     std::vector<char> site_exact;     // per tile: its preconditioner was built at its own point
     std::vector<double> lob_prev;     // per tile: xi after the previous step
     std::vector<int> stag, cert_next, cert_fail;   // per tile: inertia-test bookkeeping
+    std::vector<char> nop;            // per tile: next iteration runs without the P block (after a repair)
+    std::vector<char> lob_bad;        // per tile: the last step broke down (S lost rank); repaired
     std::vector<zd> h_zt;             // per tile: current grid point
     DBuf<int> d_cdimt, d_pcols;       // per tile: width of S, width of P
     void lob_start(const std::vector<int>& L, uint64_t seed);
+    // ||C(z) x_1|| / ||x_1|| with C(z) X recomputed explicitly, per tile of L
+    std::vector<double> explicit_rq(const std::vector<int>& L);
     // returns the tiles that finished (converged, or at max_iters: ok = 0)
     void lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>& done, std::vector<int>& ok);
     void update_store(const std::vector<int>& L);

@@ -81,7 +81,7 @@ __global__ void k_scale_cols_rsqrt(const int* list, zd* A, int64_t stride, int64
 // ---------------------------------------------------------------------------
 int KProf::begin(hipStream_t s, int c, double fl, double by)
 {
-    if (!on) return -1;
+    if (!on || (c >= 5 && level < 2)) return -1;
     if (2 * used + 2 > ev.size()) {
         size_t old = ev.size();
         ev.resize(std::max<size_t>(64, 2 * old));
@@ -101,7 +101,7 @@ void KProf::end(hipStream_t s, int idx)
 }
 void KProf::collect(ps_stats& st)
 {
-    for (int c = 0; c < 4; ++c) { st.k_launches[c] = 0; st.k_ms[c] = 0; st.k_flops[c] = 0; st.k_bytes[c] = 0; }
+    for (int c = 0; c < PS_NCLASS; ++c) { st.k_launches[c] = 0; st.k_ms[c] = 0; st.k_flops[c] = 0; st.k_bytes[c] = 0; }
     for (size_t i = 0; i < used; ++i) {
         float ms = 0.f;
         HIPCHK(hipEventSynchronize(ev[2 * i + 1]));
@@ -120,14 +120,37 @@ KProf::~KProf()
 }
 
 // ---------------------------------------------------------------------------
+void Engine::h2d(void* dst, const void* src, size_t bytes)
+{
+    if (bytes == 0) return;
+    const size_t cap = (size_t)8 << 20;
+    if (!ring.p) ring.alloc(cap);
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (need > cap) {
+        // larger than the ring: a synchronous copy from the caller's memory
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return;
+    }
+    if (ring_pos + need > cap) {
+        // every earlier slice must have been read before it is overwritten
+        HIPCHK(hipStreamSynchronize(st));
+        ring_pos = 0;
+    }
+    memcpy(ring.p + ring_pos, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, ring.p + ring_pos, bytes, hipMemcpyHostToDevice, st));
+    ring_pos += need;
+}
+
 void Engine::upload_list(const std::vector<int>& L, DBuf<int>& dst)
 {
-    h_list.alloc(L.size() + 1);
-    for (size_t i = 0; i < L.size(); ++i) h_list[i] = L[i];
-    dst.alloc(std::max<size_t>(L.size(), 1));
-    if (!L.empty()) HIPCHK(hipMemcpyAsync(dst.p, h_list.p, L.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    // h_list is reused by the next call: wait for the copy
-    HIPCHK(hipStreamSynchronize(st));
+    if (dst.n < std::max<size_t>(L.size(), 1)) {
+        // reallocation frees the old buffer: earlier work on the stream may still read it
+        HIPCHK(hipStreamSynchronize(st));
+        dst.alloc(std::max<size_t>(L.size(), 1));
+    }
+    if (!L.empty()) h2d(dst.p, L.data(), L.size() * sizeof(int));
 }
 
 void Engine::gram(const int* dlist, int nt, const BlockList& A, const BlockList& Bl, int camax, int cbmax,
@@ -161,7 +184,10 @@ void Engine::gram(const int* dlist, int nt, const BlockList& A, const BlockList&
     cr = std::max<int64_t>(32, (cr + 31) / 32 * 32);
     while ((rows + cr - 1) / cr > cap) cr += 32;
     g.chunk_rows = (int)cr;
+    int pi = prof.begin(st, 6, 8.0 * (double)rows * camax * cbmax * nt * (dd ? 4.0 : 1.0),
+                        16.0 * (double)rows * (camax + cbmax) * nt);
     launch_gram(g, st);
+    prof.end(st, pi);
 }
 
 void Engine::gemm_ts(const int* dlist, int nt, const BlockList& A, int camax, const zd* G, int64_t strideG, int ldG,
@@ -189,7 +215,10 @@ void Engine::gemm_ts(const int* dlist, int nt, const BlockList& A, int camax, co
     g.camax = camax;
     g.cbmax = cbdims ? K * cbmul : cb;
     if (cbdims) g.cbmax = std::max(g.cbmax, cb);
+    int pi = prof.begin(st, 6, 8.0 * (double)rows * camax * g.cbmax * nt,
+                        16.0 * (double)rows * (camax + g.cbmax * (beta != 0.0 ? 2 : 1)) * nt);
     launch_gemm_ts(g, st);
+    prof.end(st, pi);
 }
 
 void Engine::colnorm2(const int* dlist, int nt, const BlockList& A, int camax, double* out, int ldo)
@@ -210,7 +239,9 @@ void Engine::colnorm2(const int* dlist, int nt, const BlockList& A, int camax, d
     cr = std::max<int64_t>(64, cr);
     while ((A.rows + cr - 1) / cr * (int64_t)nt * camax > (int64_t)norm_ws.n) cr *= 2;
     a.chunk_rows = (int)cr;
+    int pi = prof.begin(st, 6, 8.0 * (double)A.rows * camax * nt, 16.0 * (double)A.rows * camax * nt);
     launch_colnorm2(a, st);
+    prof.end(st, pi);
 }
 
 // R (c x c upper) of the tall matrix A from a double-double Gram matrix and
@@ -218,7 +249,7 @@ void Engine::colnorm2(const int* dlist, int nt, const BlockList& A, int camax, d
 // double-double accuracy, so R equals the R factor of a backward-stable QR
 // of A up to rounding of R itself.
 void Engine::r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul,
-                      int cfixed, zd* R, int64_t strideR, int ldR)
+                      int cfixed, zd* R, int64_t strideR, int ldR, int* nzero)
 {
     if (nt <= 0) return;
     gram(dlist, nt, A, A, cmax, cmax, gdd.p, (int64_t)cmax * cmax, cmax, true, true);
@@ -234,7 +265,10 @@ void Engine::r_factor(const int* dlist, int nt, const BlockList& A, int cmax, co
     c.R = R;
     c.strideR = strideR;
     c.ldR = ldR;
+    c.nzero = nzero;
+    int pi = prof.begin(st, 5, 0.0, 0.0);
     launch_chol_dd(c, nt, st);
+    prof.end(st, pi);
 }
 
 // Orthonormalise the cols-column block W of each tile in L (in place), and
@@ -248,7 +282,11 @@ void Engine::orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, 
     if (nt == 0) return;
     BlockList Wl = bl_empty(rows);
     bl_add(Wl, W, wstride, ldw, cols, nullptr, 0);
-    for (int pass = 0; pass < 6; ++pass) {
+    // the last pass orthonormalises what the previous one refilled and
+    // refills nothing: a direction it still drops stays zero, which the
+    // callers detect (zero pivot of the next R factor) and repair
+    const int npass = 7;
+    for (int pass = 0; pass < npass; ++pass) {
         if (against) {
             for (int rep = 0; rep < 2; ++rep) {
                 gram(dlist, nt, *against, Wl, against_max, cols, Csm.p, (int64_t)K * 3 * r, against_max, false,
@@ -277,10 +315,13 @@ void Engine::orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, 
         sa.strideT = (int64_t)9 * r * r;
         sa.ldT = 3 * r;
         sa.mask = mask.p;
+        int pi = prof.begin(st, 5, 0.0, 0.0);
         launch_svqb(sa, nt, st);
+        prof.end(st, pi);
         gemm_ts(dlist, nt, Wl, cols, Tsm.p, (int64_t)9 * r * r, 3 * r, nullptr, 0, cols, Tn1.p, (int64_t)m * 3 * r,
                 m, rows, 1.0, 0.0);
         launch_copy_cols(dlist, nt, Tn1.p, (int64_t)m * 3 * r, m, W, wstride, ldw, rows, cols, st);
+        if (pass == npass - 1) break;
         launch_randfill(dlist, nt, W, wstride, ldw, rows, cols, mask.p, seed + 7919ull * pass, st);
         if (pass == 0) continue;
         // check whether any direction was refilled in this pass
@@ -496,6 +537,8 @@ void Engine::size_for(int tiles)
     stag.assign(t, 0);
     cert_next.assign(t, 0);
     cert_fail.assign(t, 0);
+    nop.assign(t, 0);
+    lob_bad.assign(t, 0);
     h_zt.assign(t, zmake(0.0, 0.0)); d_list2.alloc(t); d_jobsrc.alloc(t);
     d_z.alloc(t);
     const size_t J = t * B;

@@ -12,8 +12,7 @@ void Engine::upload_k()
     h_small.alloc(T + 8);
     int* hp = (int*)h_small.p;
     for (int t = 0; t < T; ++t) hp[t] = tiles[t].k;
-    HIPCHK(hipMemcpyAsync(d_k.p, hp, sizeof(int) * T, hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    h2d(d_k.p, hp, sizeof(int) * T);
 }
 
 // updateRecy with r_breve = 1 (Alg. 2, Sec. 2.2.2) for every tile in L; the
@@ -99,9 +98,8 @@ void Engine::update_store(const std::vector<int>& Lin)
         h_small.alloc(2 * T + 8);
         int* hl = (int*)h_small.p;
         for (int t = 0; t < T; ++t) { hl[t] = lsel[t]; hl[T + t] = qsel[t]; }
-        HIPCHK(hipMemcpyAsync(d_l.p, hl, sizeof(int) * T, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(d_q.p, hl + T, sizeof(int) * T, hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
+        h2d(d_l.p, hl, sizeof(int) * T);
+        h2d(d_q.p, hl + T, sizeof(int) * T);
     }
     // 2. block Gram-Schmidt against the kept blocks V_l = V[:, l r : p r]
     BlockList Lvl = bl_empty(n);
@@ -125,7 +123,10 @@ void Engine::update_store(const std::vector<int>& Lin)
     ro.Qt = Qt.p;
     ro.strideQt = (int64_t)K * K;
     ro.ldQt = K;
+    int pi = prof.begin(st, 5, 0.0, 0.0);
     launch_rotations(ro, nt, pmax - 1, st);
+    prof.end(st, pi);
+    stats.store_updates += nt;
     // 3. operator blocks of the new basis block (before rotation)
     const int64_t sT1 = (int64_t)m * 3 * r;
     launch_zero(Tn1.p, (int64_t)T * sT1, st);
@@ -196,6 +197,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     auto t_start = std::chrono::steady_clock::now();
     memset(&stats, 0, sizeof(stats));
     prof.on = P.profile != 0;
+    prof.level = P.profile;
     prof.used = 0;
     const int nx = g->nx, ny = g->ny;
     const int64_t npts = (int64_t)nx * ny;
@@ -208,8 +210,24 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         }
     const int b = std::max(1, P.batch);
     B = b;
-    int ty = P.tiles_y > 0 ? P.tiles_y : (ny + b - 1) / b;
-    int tx = P.tiles_x > 0 ? P.tiles_x : std::max(1, (int)std::lround(nx / 20.0));
+    // Default partition: tiles of about tile_points points each, as many as
+    // the per-tile device state allows within tile_mem_gb (stores, LOBPCG
+    // blocks and work arrays, ~16 (8 n K + 14 n r) bytes per tile).  Every
+    // tile is one point in flight; many tiles keep the batched products wide.
+    int tx = P.tiles_x, ty = P.tiles_y;
+    if (tx <= 0 || ty <= 0) {
+        const double per_tile = 16.0 * (8.0 * (double)std::max(m, n) * K + 14.0 * (double)std::max(m, n) * r);
+        const double cap_t = std::max(1.0, (double)P.tile_mem_gb * 1e9 / per_tile);
+        double want = std::max(1.0, std::min((double)npts / std::max(1, P.tile_points), cap_t));
+        if (tx <= 0 && ty <= 0) {
+            tx = (int)std::max(1L, std::lround(sqrt(want * nx / (double)ny)));
+            ty = (int)std::max(1L, std::lround(want / tx));
+        } else if (tx <= 0) {
+            tx = (int)std::max(1L, std::lround(want / ty));
+        } else {
+            ty = (int)std::max(1L, std::lround(want / tx));
+        }
+    }
     ty = std::min(ty, ny);
     tx = std::min(tx, nx);
     tile_orders(nx, ny, tx, ty, b, tiles);
@@ -232,6 +250,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     std::vector<int> state(T, 0);
     uint64_t step_seed = P.seed ^ 0x9e3779b97f4a7c15ull;
     int64_t loops = 0;
+    auto t_last_print = std::chrono::steady_clock::now();
     const double EPSM_E = 2.220446049250313e-16;
     const double tau_c = P.tol_abs * nC;          // certification half-width
     bool redo_pass = false;                       // Lipschitz re-refinement: no store updates
@@ -268,7 +287,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     std::vector<int> pending;                     // tiles waiting for an inertia test
     std::vector<char> cluster(T, 0);              // the tile's last refinement ended by the inertia test
     std::vector<char> cert_pend(T, 0), cert_ok(T, 0);
-    std::vector<double> cert_mu(T, 0.0);
+    std::vector<double> cert_mu(T, 0.0), cert_xi(T, 0.0);
     std::vector<int64_t> cert_since(T, 0);
     auto run_tiles = [&]() {
     pending.clear();
@@ -305,9 +324,9 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                         h_z[j] = zs[jp[j]];
                         hn[j] = nC + sqrt(zabs2(zs[jp[j]]));
                     }
-                    HIPCHK(hipMemcpyAsync(j_tile.p, hjt, sizeof(int) * nj, hipMemcpyHostToDevice, st));
-                    HIPCHK(hipMemcpyAsync(j_z.p, h_z.p, sizeof(zd) * nj, hipMemcpyHostToDevice, st));
-                    HIPCHK(hipMemcpyAsync(j_nrm.p, hn, sizeof(double) * nj, hipMemcpyHostToDevice, st));
+                    h2d(j_tile.p, hjt, sizeof(int) * nj);
+                    h2d(j_z.p, h_z.p, sizeof(zd) * nj);
+                    h2d(j_nrm.p, hn, sizeof(double) * nj);
                     RitzArgs ra;
                     memset(&ra, 0, sizeof(ra));
                     ra.njobs = nj;
@@ -337,7 +356,8 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     ra.strideG = (int64_t)K * r;
                     ra.ldG = K;
                     ra.accept = j_acc.p;
-                    int pi = prof.begin(st, 2, 0.0, 0.0);
+                    stats.ritz_jobs += nj;
+                    int pi = prof.begin(st, 2, 250.0 * K * K * K * (double)nj, 16.0 * 20.0 * K * K * (double)nj);
                     launch_ritz(ra, K, st);
                     prof.end(st, pi);
                     HIPCHK(hipGetLastError());
@@ -467,7 +487,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 else { Rv.push_back(R[i]); hsrc[R[i]] = Rsrc[i]; }
             }
             if (!Rv.empty()) {
-                HIPCHK(hipMemcpyAsync(d_jobsrc.p, hsrc, sizeof(int) * T, hipMemcpyHostToDevice, st));
+                h2d(d_jobsrc.p, hsrc, sizeof(int) * T);
                 upload_list(Rv, d_list);
                 launch_gather(d_list.p, (int)Rv.size(), d_jobsrc.p, j_G.p, (int64_t)K * r, X0c.p, (int64_t)K * r,
                               (int64_t)K * r, st);
@@ -560,7 +580,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             h_z.alloc((size_t)T + 8);
             for (int t : R) h_zt[t] = zs[tiles[t].order[tiles[t].cursor]];
             for (int t = 0; t < T; ++t) h_z[t] = h_zt[t];
-            HIPCHK(hipMemcpyAsync(d_z.p, h_z.p, sizeof(zd) * T, hipMemcpyHostToDevice, st));
+            h2d(d_z.p, h_z.p, sizeof(zd) * T);
             step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
             lob_start(R, step_seed);
             for (int t : R) {
@@ -627,6 +647,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     if ((stag[t] >= 2 && lob_it[t] >= cert_next[t]) || period) {
                         cert_pend[t] = 1;
                         cert_mu[t] = (xi - tau_c) * (xi - tau_c) + slack;
+                        cert_xi[t] = xi;
                         cert_since[t] = loops;
                         pending.push_back(t);
                     }
@@ -647,7 +668,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             for (int t : run)
                 if (cert_ok[t]) {
                     cert_ok[t] = 0;
-                    if (!isfin[t]) certified[t] = 1;
+                    if (!isfin[t] && !lob_bad[t]) certified[t] = 1;
                 }
             // inertia tests wait (while their refinements keep iterating) until
             // a full batch is pending, the oldest has waited 10 steps, or
@@ -672,7 +693,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     for (size_t i = 0; i < pending.size(); ++i) {
                         const int t = pending[i];
                         cert_pend[t] = 0;
-                        if (pd[i]) certified[t] = 1;
+                        if (pd[i] && !lob_bad[t]) certified[t] = 1;
                         else { cert_fail[t]++; cert_next[t] = lob_it[t] + 10; }
                     }
                     pending.clear();
@@ -703,13 +724,27 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     }
                 }
             }
-            for (int t = 0; t < T; ++t)
-                if (certified[t]) {
-                    fin.push_back(t);
-                    okv.push_back(2);
-                    lob_sigma[t] = lob_xi[t];
-                    stats.certified++;
+            // a certified tile returns the explicit Rayleigh quotient
+            // ||C(z) x_1|| of its current vector; the certificate holds for
+            // it when that value is within 0.2 tau above the value tested
+            // (the interval [xi_c - tau, rq] then has width <= 1.2 tau)
+            {
+                std::vector<int> cl;
+                for (int t = 0; t < T; ++t) if (certified[t]) cl.push_back(t);
+                std::vector<double> rq = explicit_rq(cl);
+                for (size_t i = 0; i < cl.size(); ++i) {
+                    const int t = cl[i];
+                    if (rq[i] <= cert_xi[t] + 0.2 * tau_c) {
+                        fin.push_back(t);
+                        okv.push_back(2);
+                        lob_sigma[t] = rq[i];
+                        stats.certified++;
+                    } else {
+                        cert_fail[t]++;
+                        cert_next[t] = lob_it[t] + 10;
+                    }
                 }
+            }
             stats.t_precond_ms += ms(te0, now());
         }
         auto t3 = now();
@@ -746,7 +781,8 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             for (int t : fin) state[t] = tiles[t].done() ? 2 : 0;
         }
         t_upd += ms(t3, now());
-        if (P.verbose && loops % 200 == 0) {
+        if (P.verbose && ms(t_last_print, now()) >= 5000.0) {
+            t_last_print = now();
             int64_t done_pts = stats.accepted + stats.refined;
             fprintf(stderr, "[ps] step %lld: points %lld/%lld accepted %lld refined %lld rebuilds %lld iters %lld  %.1f s\n",
                     (long long)loops, (long long)done_pts, (long long)npts, (long long)stats.accepted,

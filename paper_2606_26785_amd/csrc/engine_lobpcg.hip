@@ -40,7 +40,9 @@ void Engine::lob_start(const std::vector<int>& L, uint64_t seed)
     ra.ldGX = r3;
     ra.xi = xi.p;
     ra.ldxi = r3;
+    int pi0 = prof.begin(st, 5, 0.0, 0.0);
     launch_rr_hl(ra, nt, r, st);
+    prof.end(st, pi0);
     BlockList Ls = bl_empty(n);
     bl_add(Ls, S.p, sS, n, r, nullptr, 0);
     gemm_ts(d_list.p, nt, Ls, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
@@ -50,6 +52,31 @@ void Engine::lob_start(const std::vector<int>& L, uint64_t seed)
     apply(true, d_list.p, nt, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r, d_z.p);
     launch_resid_xi(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
     for (int t : L) lob_it[t] = 0;
+}
+
+std::vector<double> Engine::explicit_rq(const std::vector<int>& L)
+{
+    std::vector<double> out(L.size(), 0.0);
+    if (L.empty()) return out;
+    const int64_t sS = (int64_t)n * 3 * r, sC = (int64_t)m * 3 * r;
+    const int r3 = 3 * r;
+    upload_list(L, d_list2);
+    const int nt = (int)L.size();
+    apply(false, d_list2.p, nt, S.p, sS, n, CS.p, sC, m, r, d_z.p);
+    BlockList Lx = bl_empty(n);
+    bl_add(Lx, S.p, sS, n, 1, nullptr, 0);
+    BlockList Lcx = bl_empty(m);
+    bl_add(Lcx, CS.p, sC, m, 1, nullptr, 0);
+    colnorm2(d_list2.p, nt, Lx, 1, nrm2.p, r3);
+    colnorm2(d_list2.p, nt, Lcx, 1, nrm2.p + 1, r3);
+    HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < L.size(); ++i) {
+        const int t = L[i];
+        const double xn2 = h_nrm2[(size_t)t * r3], cn2 = h_nrm2[(size_t)t * r3 + 1];
+        out[i] = (xn2 > 0.0) ? sqrt(std::max(cn2, 0.0) / xn2) : INFINITY;
+    }
+    return out;
 }
 
 // One iteration for every tile in L:
@@ -71,17 +98,18 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
         h_small.alloc(2 * T + 8);
         int* hc = (int*)h_small.p;
         for (int t = 0; t < T; ++t) {
-            bool hasP = lob_it[t] > 0;
+            bool hasP = lob_it[t] > 0 && !nop[t];
             hc[t] = hasP ? 3 * r : 2 * r;
             hc[T + t] = hasP ? r : 0;
         }
-        HIPCHK(hipMemcpyAsync(d_cdimt.p, hc, sizeof(int) * T, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(d_pcols.p, hc + T, sizeof(int) * T, hipMemcpyHostToDevice, st));
+        h2d(d_cdimt.p, hc, sizeof(int) * T);
+        h2d(d_pcols.p, hc + T, sizeof(int) * T);
     }
     // W <- K^{-1} W into S[:, r:2r]
     if (use_prec) {
         std::vector<int> Lk, Li;
         for (int t : L) (usek[t] ? Lk : Li).push_back(t);
+        stats.precond_iters += (int64_t)Lk.size();
         upload_list(Li, d_listI);
         precond_apply(Lk, Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
         launch_copy_cols(d_listI.p, (int)Li.size(), Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r,
@@ -98,6 +126,7 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
     BlockList Lcs = bl_empty(m);
     bl_add(Lcs, CS.p, sC, m, 0, d_cdimt.p, 1);
     r_factor(d_list.p, nt, Lcs, r3, d_cdimt.p, 1, 0, Rsm.p, (int64_t)9 * r * r, r3);
+    for (int t : L) nop[t] = 0;
     RRArgs ra;
     memset(&ra, 0, sizeof(ra));
     ra.list = d_list.p;
@@ -113,7 +142,9 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
     ra.ldGX = r3;
     ra.xi = xi.p;
     ra.ldxi = r3;
+    int pi0 = prof.begin(st, 5, 0.0, 0.0);
     launch_rr_hl(ra, nt, r3, st);
+    prof.end(st, pi0);
     BlockList Ls = bl_empty(n);
     bl_add(Ls, S.p, sS, n, 0, d_cdimt.p, 1);
     gemm_ts(d_list.p, nt, Ls, r3, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, Sn.p, sS, n, n, 1.0, 0.0);
@@ -134,39 +165,89 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
     residual(d_list.p, nt);
     BlockList Lw = bl_empty(n);
     bl_add(Lw, Wres.p, (int64_t)n * r, n, r, nullptr, 0);
+    BlockList Lx = bl_empty(n);
+    bl_add(Lx, S.p, sS, n, r, nullptr, 0);
+    BlockList Lcx = bl_empty(m);
+    bl_add(Lcx, CS.p, sC, m, r, nullptr, 0);
+    // per tile, at stride 3r: residual norms^2 (columns 0..r), ||x_j||^2 (r..2r)
     colnorm2(d_list.p, nt, Lw, r, nrm2.p, r3);
+    colnorm2(d_list.p, nt, Lx, r, nrm2.p + r, r3);
     HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_xi.p, xi.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const double nC = op.normC;
+    // The Rayleigh-Ritz-SVD takes S as orthonormal.  If S lost rank (a
+    // direction of W or P that collapsed), the singular values of R are not
+    // Ritz values of C(z): the right vector of a spurious zero selects the
+    // collapsed direction, and the new X then has a column far from unit
+    // norm.  Such a step is a breakdown: the block X is orthonormalised
+    // again, C(z) X recomputed, and the next iteration runs without P.  (A
+    // zero pivot in the R factor alone is no breakdown: near the spectrum
+    // C(z) has singular values far below the rounding of its Gram matrix.)
+    auto xdev = [&](int t, int off) {
+        double d = 0.0;
+        for (int j = 0; j < r; ++j) d = std::max(d, fabs(h_nrm2[(size_t)t * r3 + off + j] - 1.0));
+        return d;
+    };
+    std::vector<int> bad;
+    for (int t : L) {
+        lob_bad[t] = !(xdev(t, r) <= 1e-6) ? 1 : 0;
+        if (lob_bad[t]) bad.push_back(t);
+    }
     // floor of eq. (tolSVD): the residual C(z)^*(C(z) x) - xi^2 x is itself
     // computed with an error of order sqrt(n) eps ||C(z)||^2, so a floor of
-    // exactly eps ||C(z)||^2 can be out of reach; the constant scales with it
+    // exactly eps ||C(z)||^2 can be out of reach; the constant scales with it.
+    // A residual w of the Hermitian N(z) = C(z)^* C(z) at the unit vector x
+    // places an eigenvalue sigma_j^2 within w of xi^2, hence |sigma_j - xi|
+    // <= w / xi: the floor branch is taken only where that bound is within
+    // tol_abs ||C||.
     const double floor_c = std::max(16.0, 4.0 * sqrt((double)n));
-    auto passes = [&](int t) {
+    auto passes = [&](int t, double x0) {
         double nz = nC + sqrt(zabs2(h_zt[t]));
-        double x0 = h_xi[(size_t)t * r3];
         double w0 = sqrt(std::max(0.0, h_nrm2[(size_t)t * r3]));
-        return w0 <= std::max(P.eta_svd * nz * x0, floor_c * nz * nz * EPSM_L) || x0 <= P.eta_abs * nC;
+        bool lin = w0 <= P.eta_svd * nz * x0;
+        bool flo = w0 <= floor_c * nz * nz * EPSM_L && w0 <= P.tol_abs * nC * x0;
+        return lin || flo || x0 <= P.eta_abs * nC;
     };
     std::vector<int> cand;
     for (int t : L) lob_xi[t] = h_xi[(size_t)t * r3];
-    for (int t : L) if (passes(t)) cand.push_back(t);
+    for (int t : L) if (!lob_bad[t] && passes(t, h_xi[(size_t)t * r3])) cand.push_back(t);
     std::vector<char> fin(T, 0);
     if (!cand.empty()) {
         // explicit recomputation of C(z) X before accepting (the implicit
-        // updates of C X drift)
+        // updates of C X drift); the value returned for the point is the
+        // Rayleigh quotient ||C(z) x_1|| / ||x_1|| of the recomputed product,
+        // an upper bound of sigma_min up to the rounding of one apply
         upload_list(cand, d_list2);
         apply(false, d_list2.p, (int)cand.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
         residual(d_list2.p, (int)cand.size());
         colnorm2(d_list2.p, (int)cand.size(), Lw, r, nrm2.p, r3);
+        colnorm2(d_list2.p, (int)cand.size(), Lcx, r, nrm2.p + r, r3);
+        colnorm2(d_list2.p, (int)cand.size(), Lx, r, nrm2.p + 2 * r, r3);
         HIPCHK(hipMemcpyAsync(h_nrm2.p, nrm2.p, sizeof(double) * T * r3, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        for (int t : cand) if (passes(t)) fin[t] = 1;
+        for (int t : cand) {
+            const double xn2 = h_nrm2[(size_t)t * r3 + 2 * r];
+            const double cn2 = h_nrm2[(size_t)t * r3 + r];
+            if (!(fabs(xn2 - 1.0) <= 1e-6)) { lob_bad[t] = 1; bad.push_back(t); continue; }
+            const double xe = sqrt(std::max(cn2, 0.0) / xn2);
+            if (passes(t, xe)) {
+                fin[t] = 1;
+                lob_sigma[t] = xe;
+            }
+        }
+    }
+    if (!bad.empty()) {
+        stats.repairs += (int64_t)bad.size();
+        upload_list(bad, d_list2);
+        orthonormalize(bad, d_list2.p, S.p, sS, n, n, r, nullptr, 0, seed ^ 0x5bd1e995ull);
+        apply(false, d_list2.p, (int)bad.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
+        residual(d_list2.p, (int)bad.size());
+        for (int t : bad) nop[t] = 1;
     }
     for (int t : L) {
         if (fin[t] || lob_it[t] >= P.max_iters) {
-            lob_sigma[t] = h_xi[(size_t)t * r3];
+            if (!fin[t]) lob_sigma[t] = h_xi[(size_t)t * r3];
             done.push_back(t);
             okv.push_back(fin[t] ? 1 : 0);
         }

@@ -114,8 +114,7 @@ void Engine::precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, z
         maxc = std::max(maxc, gcnt[g]);
     }
     for (int i = 0; i < nt; ++i) h[3 * ng + i] = order[i];
-    HIPCHK(hipMemcpyAsync(d_gmap.p, h, sizeof(int) * (3 * ng + nt), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    h2d(d_gmap.p, h, sizeof(int) * (3 * ng + nt));
     const int64_t nn = n * n;
     stats.sv_F += (int64_t)2 * nt * r;
     const int* gm = d_gmap.p + ng;
@@ -156,7 +155,7 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
             h_z[i] = sites[b0 + i];
             zmax = std::max(zmax, sqrt(zabs2(sites[b0 + i])));
         }
-        HIPCHK(hipMemcpyAsync(d_zdag.p, h_z.p, sizeof(zd) * nb, hipMemcpyHostToDevice, st));
+        h2d(d_zdag.p, h_z.p, sizeof(zd) * nb);
         const double scale = (op.normC + zmax) * (op.normC + zmax);
         const double delta = 1e-13 * scale;
         h_shift.alloc((size_t)nb + 8);
@@ -164,9 +163,11 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
             double mv = mu ? (*mu)[b0 + i] : 0.0;
             h_shift[i] = (mv == 0.0) ? delta : -mv;
         }
-        HIPCHK(hipMemcpyAsync(d_shift.p, h_shift.p, sizeof(double) * nb, hipMemcpyHostToDevice, st));
+        h2d(d_shift.p, h_shift.p, sizeof(double) * nb);
         HIPCHK(hipMemsetAsync(d_notpd.p, 0, sizeof(int) * nb, st));
+        int pf = prof.begin(st, 4, 8.0 * (double)nn * nb, 16.0 * 4.0 * (double)nn * nb);
         launch_form_normal(dl, nb, CtC.p, op.A.p, m, op.AH.p, n, d_zdag.p, d_shift.p, PN.p, nn, st);
+        prof.end(st, pf);
         if (!cert_only) launch_zero_tiles(dl, nb, Fb.p, nn, nn, st);
         // two-level blocked Cholesky: outer blocks of PRE_OB columns updated
         // right-looking (one rank-PRE_OB trailing product per outer block,
@@ -182,8 +183,11 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
                           PN.p + k0 + k0 * n, n, nn, -1.0, 1.0);
                 }
                 // diagonal block and row panel R[k, k1:] = R_kk^{-*} A[k, k1:] in one launch
+                const int pc = prof.begin(st, 4, 8.0 * nb * ((double)kb * kb * kb / 3.0 + (double)kb * kb * (n - k0 - kb)),
+                                          16.0 * nb * (double)kb * (n - k0) * 2.0);
                 launch_chol_step(dl, nb, PN.p, nn, n, k0, kb, cert_only ? nullptr : Dinv.p, (int64_t)n * PRE_NB,
                                  cert_only ? nullptr : Fb.p, nn, 1e-2 * delta, d_notpd.p, st);
+                prof.end(st, pc);
                 if (!cert_only && k0 > K0) {
                     // F^{-1}[K0:k0, k] = -F^{-1}[K0:k0, K0:k0] R[K0:k0, k] R_kk^{-1}
                     zgemm(dl, nb, k0 - K0, kb, k0 - K0, Fb.p + K0 + K0 * n, n, nn, 0, PN.p + K0 + k0 * n, n, nn,

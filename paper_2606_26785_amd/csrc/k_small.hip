@@ -346,11 +346,15 @@ __global__ void __launch_bounds__(NT) k_chol_dd(CholArgs a)
     zd* R = a.R + (size_t)tile * a.strideR;
     const int ldg = a.ldG, ldr = a.ldR;
     const int tid = threadIdx.x;
-    if (c <= 0) return;
+    if (c <= 0) {
+        if (tid == 0 && a.nzero) a.nzero[tile] = 0;
+        return;
+    }
     double dmax = 0;
     for (int i = tid; i < c; i += blockDim.x) dmax = fmax(dmax, G[i + (size_t)i * ldg].x.hi);
     dmax = block_max(dmax, red);
     const double thr = (double)c * 1e-30 * dmax;
+    int nzero = 0;
     for (int j = 0; j < c; ++j) {
         if (tid == 0) {
             ddv d = G[j + (size_t)j * ldg].x;
@@ -360,6 +364,7 @@ __global__ void __launch_bounds__(NT) k_chol_dd(CholArgs a)
         __syncthreads();
         const int zr = zero_s;
         const ddv piv = piv_s;
+        nzero += zr;
         for (int kk = j + tid; kk < c; kk += blockDim.x) {
             zdd v;
             if (zr) v = zdd_zero();
@@ -383,6 +388,7 @@ __global__ void __launch_bounds__(NT) k_chol_dd(CholArgs a)
         }
         __syncthreads();
     }
+    if (tid == 0 && a.nzero) a.nzero[tile] = nzero;
 }
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,7 @@ struct CholArgs {
     int cmul, c;
     zdd* G; int64_t strideG; int ldG;
     zd* R; int64_t strideR; int ldR;
+    int* nzero;            // per tile: pivots treated as zero (NULL: not reported)
 };
 struct RRArgs {
     const int* list;

@@ -32,6 +32,8 @@ void ps_default_params(ps_params* p)
     p->precond = -1;
     p->tiles_x = 0;
     p->tiles_y = 0;
+    p->tile_points = 20;
+    p->tile_mem_gb = 48;
     p->batch = 20;
     p->recycle = 1;
     p->eta = 1e-6;
@@ -90,6 +92,7 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
     if (p.kbar_max < p.rbar || p.kbar_max % p.rbar || p.kbar_max > 64)
         return fail(PS_EINVAL, "kbar_max must be a multiple of rbar, <= 64");
     if (p.max_iters < 1 || p.batch < 1) return fail(PS_EINVAL, "max_iters and batch must be positive");
+    if (p.tile_points < 1 || p.tile_mem_gb < 1) return fail(PS_EINVAL, "tile_points and tile_mem_gb must be positive");
     if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0) || !(p.eta_abs >= 0) || p.eta_abs > 1e-8 ||
         !(p.tol_abs >= 0) || p.tol_abs > 1e-6 || p.esc_iters < 0)
         return fail(PS_EINVAL, "bad tolerances");

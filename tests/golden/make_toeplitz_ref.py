@@ -8,8 +8,12 @@ nothing here calls the GPU library.  Output: a float64 .npy of nx*ny values
 in grid order (index j*nx + i) and a small JSON file with the workload
 fingerprint.  Runs for hours on a few cores; progress goes to stderr and
 finished chunks are kept in <out>.part so an interrupted run resumes.
+The JSON file also holds ||C||_2, the largest singular value of C from the
+same oracle at z = 0 (all n singular values by Sturm bisection); it scales
+the parity tolerance.  ``--norm`` (re)computes only that value.
 
     OMP_NUM_THREADS=8 python tests/golden/make_toeplitz_ref.py
+    python tests/golden/make_toeplitz_ref.py --norm
 """
 import json
 import os
@@ -34,8 +38,20 @@ def fingerprint(wl):
             "c01": [float(wl.dense[0, 1].real), float(wl.dense[0, 1].imag)]}
 
 
+def norm2(wl):
+    band, kl, ku = oracle.band_from_dense(wl.dense)
+    return float(oracle.banded_smallest(band, wl.m, wl.n, kl, ku, 0.0, k=wl.n)[-1])
+
+
 def main():
     wl = workloads.toeplitz_band()
+    meta_path = OUT.replace(".npy", ".json")
+    if "--norm" in sys.argv[1:]:
+        meta = json.load(open(meta_path))
+        meta["normC"] = norm2(wl)
+        with open(meta_path, "w") as f:
+            json.dump(meta, f)
+        return
     zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
     band, kl, ku = oracle.band_from_dense(wl.dense)
     part = OUT + ".part.npy"
@@ -49,8 +65,8 @@ def main():
         np.save(part, sig)
         print("%d/%d points, %.0f s" % (c1, zs.size, time.time() - t0), file=sys.stderr, flush=True)
     np.save(OUT, sig)
-    with open(OUT.replace(".npy", ".json"), "w") as f:
-        json.dump(dict(fingerprint(wl), threads=oracle.num_threads(), oracle="O2 banded"), f)
+    with open(meta_path, "w") as f:
+        json.dump(dict(fingerprint(wl), threads=oracle.num_threads(), oracle="O2 banded", normC=norm2(wl)), f)
     os.remove(part)
 
 

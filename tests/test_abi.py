@@ -37,7 +37,7 @@ def _struct_fields(name):
         decl = decl.strip()
         if not decl:
             continue
-        decl = re.sub(r"\[\d+\]", "", decl)
+        decl = re.sub(r"\[\w+\]", "", decl)
         for part in decl.split(","):
             fields.append(re.findall(r"\w+", part)[-1])
     return fields

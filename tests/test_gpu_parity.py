@@ -2,12 +2,17 @@
 
 The bar: |sigma_gpu - sigma_ref| <= 1e-8 ||C||_2 at every oracle point,
 identical epsilon-membership wherever |sigma_ref - eps| > 1e-8 ||C||_2, and
-no value noticeably below the true sigma_min: Ritz values are upper bounds
-(Courant-Fischer) in exact arithmetic, and in floating point they can fall
-below only through the orthonormality error of the basis, so
-sigma_gpu >= sigma_ref - 1e-9 ||C||_2 (misconvergence to a larger singular
-value shows up in the first bound instead).
+no value below the true sigma_min beyond rounding: every value the library
+returns is a Ritz value or an explicitly recomputed Rayleigh quotient
+||C(z) x|| / ||x||, an upper bound of sigma_min (Courant-Fischer) up to the
+rounding of one operator apply (~ sqrt(n) eps ||C||), so
+sigma_gpu >= sigma_ref - 1e-11 ||C||_2.  Misconvergence to a larger singular
+value shows up in the first bound instead.
+
+||C||_2, which scales both bounds, comes from the oracle: the largest
+singular value of C by O1 (dense) or O2 (banded), never from the library.
 """
+import functools
 import os
 
 import numpy as np
@@ -21,6 +26,30 @@ P = pytest.importorskip("paper_2606_26785_amd")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-8
+LOW = 1e-11
+
+
+def _norm_dense(C):
+    return float(oracle.singular_values_dense(C)[0])
+
+
+@functools.lru_cache(maxsize=None)
+def _toeplitz_norm():
+    meta = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "toeplitz_n4000_grid200_sigma.json")
+    if os.path.exists(meta):
+        import json
+        v = json.load(open(meta)).get("normC")
+        if v:
+            return float(v)            # written by make_toeplitz_ref.py from the oracle
+    wl = workloads.toeplitz_band()
+    band, kl, ku = oracle.band_from_dense(wl.dense)
+    return float(oracle.banded_smallest(band, wl.n, wl.n, kl, ku, 0.0, k=wl.n)[-1])
+
+
+def _o1(C, zs):
+    ref, sweeps = oracle.sigma_min_dense(C, zs)
+    assert (sweeps > 0).all(), "oracle O1 hit its sweep cap at %d points" % int((sweeps <= 0).sum())
+    return ref
 
 
 def _cplx(rng, *shape):
@@ -31,13 +60,14 @@ def _check_parity(wl, res, ref, normC, label):
     sig = res.sigma
     err = np.abs(sig - ref)
     bad = np.nonzero(err > TOL * normC)[0]
-    low = np.nonzero(sig < ref - 1e-9 * normC)[0]
+    low = np.nonzero(sig < ref - LOW * normC)[0]
     print("%s: max|err|/|C| = %.3e, points %d, stats %s" % (label, err.max() / normC, sig.size,
                                                            {k: res.stats[k] for k in ("accepted", "refined",
                                                             "uncertified", "lobpcg_iters", "rounds",
                                                             "t_total_ms")}), flush=True)
     assert bad.size == 0, "%s: %d points off, worst %g at %d" % (label, bad.size, err.max(), int(np.argmax(err)))
-    assert low.size == 0, "%s: %d Ritz values below sigma_min" % (label, low.size)
+    assert low.size == 0, "%s: %d values below sigma_min, worst %g at %d" % (
+        label, low.size, float((ref - sig).max()), int(np.argmax(ref - sig)))
     if len(wl.eps):
         mem_ref = oracle.membership(ref, wl.eps)
         far = np.abs(ref[None, :] - np.asarray(wl.eps)[:, None]) > TOL * normC
@@ -87,34 +117,33 @@ def _run(wl, **pk):
     mat = P.create_from_workload(wl, params=params)
     g = P.ps_grid(*wl.region, wl.nx, wl.ny)
     res = P.ps_eval(mat, g, wl.eps)
-    normC = mat.norm_estimate / 1.01
     mat.close()
-    return res, normC
+    return res
 
 
 def test_triangular_small_grid_parity():
     wl = workloads.triangular_disk(seed=1001, n=100, grid=12)
     zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
-    ref, _ = oracle.sigma_min_dense(wl.dense, zs)
-    res, nC = _run(wl)
-    _check_parity(wl, res, ref, nC, "triangular n=100 12x12")
+    ref = _o1(wl.dense, zs)
+    res = _run(wl)
+    _check_parity(wl, res, ref, _norm_dense(wl.dense), "triangular n=100 12x12")
 
 
 def test_plain_solver_parity():
     wl = workloads.triangular_disk(seed=1001, n=100, grid=8)
     zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
-    ref, _ = oracle.sigma_min_dense(wl.dense, zs)
-    res, nC = _run(wl, recycle=0)
+    ref = _o1(wl.dense, zs)
+    res = _run(wl, recycle=0)
     assert res.stats["accepted"] == 0 and res.stats["refined"] == wl.npts
-    _check_parity(wl, res, ref, nC, "plain n=100 8x8")
+    _check_parity(wl, res, ref, _norm_dense(wl.dense), "plain n=100 8x8")
 
 
 def test_triangular_full_grid_parity():
     wl = workloads.triangular_disk()          # n = 100, 50 x 50 over [-2, 2]^2
     zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
-    ref, _ = oracle.sigma_min_dense(wl.dense, zs)
-    res, nC = _run(wl)
-    _check_parity(wl, res, ref, nC, "triangular n=100 50x50")
+    ref = _o1(wl.dense, zs)
+    res = _run(wl)
+    _check_parity(wl, res, ref, _norm_dense(wl.dense), "triangular n=100 50x50")
     assert res.stats["accepted"] > 0
 
 
@@ -123,7 +152,8 @@ def test_toeplitz_reduced_parity():
     zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
     band, kl, ku = oracle.band_from_dense(wl.dense)
     ref = oracle.sigma_min_banded(band, wl.n, wl.n, kl, ku, zs)
-    res, nC = _run(wl)
+    nC = float(oracle.banded_smallest(band, wl.n, wl.n, kl, ku, 0.0, k=wl.n)[-1])
+    res = _run(wl)
     _check_parity(wl, res, ref, nC, "toeplitz n=400 24x24")
 
 
@@ -132,7 +162,8 @@ def test_folding_rectangular_parity():
     zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
     band, kl, ku = oracle.band_from_csr(wl.m, wl.n, wl.rowptr, wl.colind, wl.vals)
     ref = oracle.sigma_min_banded(band, wl.m, wl.n, kl, ku, zs)
-    res, nC = _run(wl)
+    nC = float(oracle.banded_smallest(band, wl.m, wl.n, kl, ku, 0.0, k=wl.n)[-1])
+    res = _run(wl)
     _check_parity(wl, res, ref, nC, "folding n=200 m=204 10x10")
 
 
@@ -160,14 +191,17 @@ def test_dense_base_preconditioner(n, m):
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "toeplitz_n4000_grid200_sigma.npy")
 
 
-@pytest.mark.parametrize("i0,j0", [(184, 0), (136, 136)])
+@pytest.mark.parametrize("i0,j0", [(184, 0), (136, 136), (176, 124)])
 def test_toeplitz_full_size_windows(i0, j0):
     """The n = 4000 dense Toeplitz matrix of the benchmark on 16 x 16 blocks of
     its full 200 x 200 grid, against the oracle values stored for those grid
     points (tests/golden, written by make_toeplitz_ref.py from the banded
     oracle): the far exterior corner, where the smallest singular values form
-    a tight cluster, and a block across the boundary of the spectrum (noise
-    level, boundary band and exterior points)."""
+    a tight cluster; a block across the boundary of the spectrum (noise
+    level, boundary band and exterior points); and a block of the boundary
+    band whose values lie between 1e-10 and 1e-8 ||C|| (grid points (180, 130)
+    and (182, 138) among them), where a rank-deficient search space once
+    produced an exact zero."""
     if not os.path.exists(GOLD):
         pytest.skip("oracle reference not generated")
     gold = np.load(GOLD).reshape(200, 200)
@@ -179,8 +213,8 @@ def test_toeplitz_full_size_windows(i0, j0):
     mat = P.create_from_workload(wl)
     g = P.ps_grid(xs[0], xs[1], ys[0], ys[1], w, w)
     res = P.ps_eval(mat, g, wl.eps)
-    normC = mat.norm_estimate / 1.01
     mat.close()
+    normC = _toeplitz_norm()
     ref = gold[j0:j0 + w, i0:i0 + w].reshape(-1)
     sub = workloads.Workload(name="window", m=wl.m, n=wl.n, kind="dense", region=(xs[0], xs[1], ys[0], ys[1]),
                              nx=w, ny=w, eps=wl.eps)

@@ -290,3 +290,20 @@ def test_o2_diagonal_matrix():
     s = oracle.sigma_min_banded(band, 4, 4, 0, 0, zs)
     ref = np.min(np.abs(d[None, :] - zs[:, None]), axis=1)
     assert np.allclose(s, ref, rtol=0, atol=1e-15)
+
+
+def test_grid_points_inclusive_endpoints_and_order():
+    # Reading of the paper's "equispaced Cartesian grid" (Sec. 4): both ends
+    # of each side are grid points, and point (i, j) sits at index j * nx + i.
+    # Pinned with hand-computed coordinates, not with the library's grid.
+    zs = oracle.grid_points(-1.0, 3.0, 2.0, 5.0, 5, 4)
+    assert zs.shape == (20,)
+    want_x = [-1.0, 0.0, 1.0, 2.0, 3.0]
+    want_y = [2.0, 3.0, 4.0, 5.0]
+    for j in range(4):
+        for i in range(5):
+            assert zs[j * 5 + i] == complex(want_x[i], want_y[j])
+    # a single point per side sits at the low end
+    assert oracle.grid_points(0.5, 9.0, -2.0, 7.0, 1, 1)[0] == complex(0.5, -2.0)
+    one_row = oracle.grid_points(0.0, 1.0, 3.0, 4.0, 3, 1)
+    assert list(one_row) == [3j, 0.5 + 3j, 1.0 + 3j]

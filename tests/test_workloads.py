@@ -4,6 +4,7 @@ import json
 import os
 
 import numpy as np
+import pytest
 
 import workloads
 
@@ -40,7 +41,7 @@ def test_seeded_draws_repeat():
 def test_golden_reference_matches_generator():
     path = os.path.join(GOLD, "toeplitz_n4000_grid200_sigma.json")
     if not os.path.exists(path):
-        return
+        pytest.skip("stored oracle values not generated")
     meta = json.load(open(path))
     wl = workloads.toeplitz_band()
     assert (meta["n"], meta["nx"], meta["ny"]) == (wl.n, wl.nx, wl.ny)
