@@ -68,6 +68,21 @@ def path_work(st, n, r, k):
     return fl, by
 
 
+def path_work_sparse(st, wl, r, k):
+    """Algorithmic HBM bytes (and flops) of one ps_eval on the sparse path
+    from the library's counters: per operator column-apply the CSR arrays
+    (20 B per nonzero) plus one read of x and one write of y (32 n B); per
+    preconditioner column-solve the factor values and indices (20 B per
+    nonzero) plus x, y; per LOBPCG iteration about 30 sweeps over n x r
+    blocks; the Ritz tests as in the dense path."""
+    nnz = float(len(wl.vals) + wl.n)
+    n = float(wl.n)
+    by = (st["mv_M"] * (20.0 * nnz / max(r, 1) + 32.0 * n) + st["sv_F"] * (20.0 * nnz / max(r, 1) + 32.0 * n)
+          + st["lobpcg_iters"] * 30.0 * n * r * 16.0)
+    fl = st["ritz_jobs"] * 250.0 * k ** 3 + 8.0 * nnz * (st["mv_M"] + st["sv_F"])
+    return fl, by
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--budget-s", type=float, default=500.0,
                     help="wall-clock budget of the whole run (timed steps stop when the next would not fit)")
+    ap.add_argument("--workload", default="toeplitz", choices=["toeplitz", "convdiff"],
+                    help="toeplitz: dense Toeplitz n=4000, 200x200 (default); convdiff: sparse CSR n=250,000, 100x100")
     ap.add_argument("--n", type=int, default=4000)
     ap.add_argument("--grid", type=int, default=200)
     ap.add_argument("--plain-stride", type=int, default=10,
@@ -105,10 +122,15 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    wl = workloads.toeplitz_band(n=args.n, grid=args.grid)
+    if args.workload == "convdiff":
+        wl = workloads.convection_diffusion()
+        params = P.default_params(profile=args.profile, verbose=0 if args.quiet else 1, tiles_x=args.tiles_x,
+                                  tiles_y=args.tiles_y, batch=args.batch, k_max=64, tile_mem_gb=96)
+    else:
+        wl = workloads.toeplitz_band(n=args.n, grid=args.grid)
+        params = P.default_params(profile=args.profile, verbose=0 if args.quiet else 1, tiles_x=args.tiles_x,
+                                  tiles_y=args.tiles_y, batch=args.batch)
     npts = wl.npts
-    params = P.default_params(profile=args.profile, verbose=0 if args.quiet else 1, tiles_x=args.tiles_x,
-                              tiles_y=args.tiles_y, batch=args.batch)
     t0 = time.perf_counter()
     mat = P.create_from_workload(wl, params=params)
     t_create = time.perf_counter() - t0
@@ -170,7 +192,8 @@ def main():
                                                        if CLASS_BOUND[i] != "hbm" else
                                                        st["k_bytes"][i] / (kms[i] * 1e-3) / 1e9 / PEAK_HBM_GBS)
                                       for i in range(len(kms)) if kms[i] > 0}}
-    fl_path, by_path = path_work(st, wl.n, params.r, params.k_max)
+    fl_path, by_path = path_work(st, wl.n, params.r, params.k_max) if wl.kind == "dense" else \
+        path_work_sparse(st, wl, params.r, params.k_max)
     t_roof = fl_path / (PEAK_FP64_TFLOPS * 1e12) + by_path / (PEAK_HBM_GBS * 1e9)
     roofline_path = {"bound": "mfma", "algorithmic_tflop": fl_path / 1e12, "algorithmic_gb": by_path / 1e9,
                      "t_roof_s": t_roof, "t_step_s": ms_per_step / 1000.0,
@@ -184,7 +207,20 @@ def main():
     parity = None
     gold = os.path.join(ROOT, "tests", "golden", "toeplitz_n4000_grid200_sigma.npy")
     meta = gold.replace(".npy", ".json")
-    if args.n == 4000 and args.grid == 200 and os.path.exists(gold) and os.path.exists(meta):
+    gold_cd = os.path.join(ROOT, "tests", "golden", "convdiff_n250000_grid100_sigma.json")
+    if args.workload == "convdiff" and os.path.exists(gold_cd):
+        d = json.load(open(gold_cd))
+        idx = np.asarray(d["indices"])
+        ref = np.asarray(d["sigma"])
+        normC = float(d["normC"])
+        err = (res.sigma[idx] - ref) / normC
+        parity = {"points": int(ref.size), "max_abs_err_over_normC": float(np.abs(err).max()),
+                  "points_over_1e-8": int((np.abs(err) > 1e-8).sum()),
+                  "min_signed_err_over_normC": float(err.min()),
+                  "oracle": "O2 sparse (banded LU + inverse subspace iteration), 64 seeded points (tests/golden)"}
+        log("sample parity: max |err|/||C|| = %.2e over %d points" % (parity["max_abs_err_over_normC"], ref.size))
+    elif args.workload == "toeplitz" and args.n == 4000 and args.grid == 200 and os.path.exists(gold) and \
+            os.path.exists(meta):
         ref = np.load(gold)
         normC = float(json.load(open(meta))["normC"])      # oracle-side ||C||_2
         err = (res.sigma - ref) / normC
@@ -219,7 +255,18 @@ def main():
         log("plain solver: %d points in %.2f s" % (nxp * nyp, tp))
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "convdiff":
+        import oracle
+        zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
+        idx = workloads.sample_indices(zs.size, 1, 4242)
+        tc0 = time.perf_counter()
+        ref, _ = oracle.sigma_min_sparse_lu(wl.m, wl.n, wl.rowptr, wl.colind, wl.vals, zs[idx], normC=8.0)
+        tc = time.perf_counter() - tc0
+        cpu = {"value": len(idx) / tc, "unit": "pts/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d seeded point of the same grid, sparse oracle O2 (banded LU with bandwidth 500 + block "
+                         "inverse subspace iteration), %.1f s wall" % (len(idx), tc)}
+        log("oracle sample: %d points in %.2f s" % (len(idx), tc))
+    elif not args.no_cpu:
         import oracle
         zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
         band, kl, ku = oracle.band_from_dense(wl.dense)
@@ -256,9 +303,13 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c128",
-        "data": "synthetic (seeded dense banded Toeplitz, stored dense)",
-        "config": {"workload": "dense-toeplitz-n%d-grid%dx%d" % (wl.n, wl.nx, wl.ny), "n": wl.n,
-                   "grid": [wl.nx, wl.ny], "r": params.r, "k_max": params.k_max, "points": npts},
+        "data": "synthetic (seeded dense banded Toeplitz, stored dense)" if args.workload == "toeplitz" else
+                "synthetic (seeded convection-diffusion CSR with random row phases)",
+        "config": {"workload": ("dense-toeplitz-n%d-grid%dx%d" if args.workload == "toeplitz" else
+                                "csr-convdiff-n%d-grid%dx%d") % (wl.n, wl.nx, wl.ny), "n": wl.n,
+                   "grid": [wl.nx, wl.ny], "r": params.r, "k_max": params.k_max, "points": npts,
+                   "precond": "base (exact Cholesky sites)" if wl.kind == "dense" else
+                              "two-level (incomplete LU base + recycled projection subspace)"},
         "stats": {k: st[k] for k in ("accepted", "refined", "uncertified", "certified", "lipschitz_redo",
                                      "lobpcg_iters", "precond_iters", "ritz_jobs", "store_updates", "rebuilds",
                                      "cert_tests", "repairs", "rounds", "mv_M", "sv_F", "t_ritz_ms",

@@ -81,20 +81,32 @@ typedef struct {
 typedef struct {
     int32_t r;          /* singular LOBPCG block size r (default 8) */
     int32_t k_max;      /* cap on the recycled singular dimension p r (default 32) */
-    int32_t rbar;       /* projection block size rbar (default 16; the
-                           projection subspace of Sec. 3.2 is not built in
-                           this version: validated, otherwise unused) */
-    int32_t kbar_max;   /* cap on the recycled projection dimension (default
-                           64; validated, otherwise unused) */
+    int32_t rbar;       /* projection block size rbar (Sec. 3.2); with the
+                           two-level preconditioner it must equal r, because
+                           the projection LOBPCG shares the singular one's
+                           block layout (default 8) */
+    int32_t kbar_max;   /* cap on the recycled projection dimension kbar
+                           per preconditioner site, a multiple of rbar,
+                           <= 64 (default 64) */
     int32_t max_iters;  /* LOBPCG iteration cap (default 300) */
-    int32_t precond;    /* LOBPCG preconditioner K (Sec. 3): 0: K = I;
-                           1: base preconditioner K = F^* F ~ N(z_dag), rebuilt
-                           by the rule of eq. (tauRecycle) (dense C: F is the
-                           Cholesky factor of N(z_dag) + delta I);
-                           -1 (default): 1 for dense C, 0 for CSR */
+    int32_t precond;    /* LOBPCG preconditioner (Sec. 3): 0: K = I;
+                           1: base preconditioner alone, K = F^* F with F
+                           the Cholesky factor of N(z_dag) + delta I, a site
+                           serving z while ((1 + g) / (1 - g))^2 <= tau_max,
+                           g = ||F^{-1}|| |z - z_dag|;
+                           2: the two-level preconditioner of eq. (twolevel)
+                           with a recycled projection subspace per site
+                           (Alg. 4 and 5), K = F^* F with F the Cholesky
+                           factor of N(z_dag) + (reg_base (||C|| + |z_dag|))^2 I,
+                           rebuilt by the rule of eq. (tauRecycle);
+                           For a square CSR C, F is instead the incomplete
+                           LU factor (no fill) of C - z_dag I in a colour
+                           ordering of its graph, K = (F P)^* (F P).
+                           -1 (default): 1 for dense C, 2 for square CSR,
+                           0 for rectangular CSR */
     int32_t tiles_x;    /* grid-front partition: tiles along x (0 = auto) */
     int32_t tiles_y;    /* tiles along y (0 = auto) */
-    int32_t tile_points;/* auto partition: points per tile (default 20) */
+    int32_t tile_points;/* auto partition: points per tile (default 80) */
     int32_t tile_mem_gb;/* auto partition: device memory for per-tile state
                            (default 48) */
     int32_t batch;      /* b of the batch-zigzag traversal (default 20) */
@@ -102,12 +114,16 @@ typedef struct {
                            seeded random start (the comparison solver) */
     double eta;         /* acceptance tolerance of eq. (tolC) (default 1e-6) */
     double eta_svd;     /* LOBPCG convergence tolerance, eq. (tolSVD) (1e-9) */
-    double eta_proj;    /* projection test tolerance, eq. (tolTz) (1e-4;
-                           unused in this version) */
+    double eta_proj;    /* relaxed tolerance of eq. (tolTz) for projection
+                           Ritz pairs and the projection LOBPCG (1e-4) */
     double omega;       /* pruning threshold of eq. (omegaCond) (1.6) */
-    double tau_min;     /* eq. (tauRecycle) lower threshold (1e-3; it bounds
-                           the projection part, unused in this version) */
-    double tau_max;     /* eq. (tauRecycle) upper threshold (30) */
+    double tau_min;     /* eq. (tauRecycle): rebuild the base preconditioner
+                           when lambda_bar_rbar < tau_min; projection columns
+                           with sigma_bar^2 <= tau_min enter the omega test
+                           (1e-3) */
+    double tau_max;     /* eq. (tauRecycle): a site serves z while
+                           (sqrt(lambda_n^dagger) + gamma |z - z_dag|)^2 <=
+                           tau_max (30) */
     double zdag_re;     /* first base-preconditioner site; NaN = region centre */
     double zdag_im;
     uint64_t seed;      /* seed of random start blocks */
@@ -136,6 +152,10 @@ typedef struct {
                            before starting LOBPCG (default 0: on the dense
                            Toeplitz workload half of those tests fail and the
                            sweep is 27% slower) */
+    double reg_base;    /* precond = 2: relative regularisation of the base
+                           preconditioner, which bounds gamma = ||F^{-1}|| by
+                           1 / (reg_base (||C|| + |z_dag|)) so that a site
+                           serves a region even near the spectrum (0.02) */
     int32_t lipschitz;  /* 1 (default): after the sweep, points whose value
                            exceeds an upper bound from a finished grid
                            neighbour (the norm of C(z) on the neighbour's

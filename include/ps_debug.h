@@ -24,6 +24,21 @@ ps_status ps_debug_apply(ps_matrix* h, int32_t herm, double z_re, double z_im, c
  * Errors: PS_EUNSUPPORTED if the handle has no dense preconditioner. */
 ps_status ps_debug_precond(ps_matrix* h, double z_re, double z_im, double* Finv, double* gamma);
 
+/* Two-level preconditioner (eq. (twolevel), Lemma 3.1): builds a
+ * regularised base site K = N(z_dag) + d I at z_dag, runs the projection
+ * LOBPCG-SVD on Mbar(z) = C(z) F^{-1} (Sec. 3.2) at z from a seeded random
+ * block, forms Ebar = F^{-1} Xbar (n x r, host, column-major) and
+ * Lambda_bar = Sigma_bar^2 (r values), and applies
+ * Y = K_Ebar^{-1} W = F^{-1} F^{-*} W + Ebar Lambda_bar^{-1} Ebar^* W to the
+ * n x r host block W.  iters (nullable) receives the LOBPCG iterations.
+ * Errors: PS_EUNSUPPORTED without precond = 2, PS_EINVAL, PS_EDEVICE. */
+ps_status ps_debug_twolevel(ps_matrix* h, double zd_re, double zd_im, double z_re, double z_im, const double* W,
+                            double* Y, double* Ebar, double* lam, int32_t* iters);
+
+/* Regularisation shift d and gamma = ||F^{-1}||_2 of the site built by the
+ * last ps_debug_twolevel call. */
+ps_status ps_debug_site(ps_matrix* h, double* dreg, double* gamma);
+
 /* The ||C||_2 estimate used in the acceptance tests (power iteration). */
 double ps_debug_norm(const ps_matrix* h);
 

@@ -202,3 +202,86 @@ def membership(sigma: np.ndarray, eps_levels) -> np.ndarray:
     """member[e, k] = sigma[k] < eps_e (strict, eq. (defSquareSVD))."""
     eps = np.asarray(eps_levels, dtype=np.float64).reshape(-1, 1)
     return (np.asarray(sigma)[None, :] < eps).astype(np.uint8)
+
+
+def norm2_sparse(m: int, n: int, rowptr, colind, vals, rel: float = 1e-10, seed: int = 7) -> float:
+    """||C||_2 of a CSR matrix by power iteration on C^* C, stopped when the
+    estimate changes by less than rel (relative).  It only scales
+    tolerances."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.asarray(vals, dtype=np.complex128), np.asarray(colind), np.asarray(rowptr)),
+                      shape=(m, n))
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x /= np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(100000):
+        y = A.conj().T @ (A @ x)
+        new = float(np.linalg.norm(y))
+        x = y / new
+        if abs(new - lam) <= rel * new:
+            lam = new
+            break
+        lam = new
+    return float(np.sqrt(lam))
+
+
+def sigma_min_sparse_lu(m: int, n: int, rowptr, colind, vals, zs, block: int = 8, tol_rel: float = 1e-14,
+                        max_iter: int = 200, seed: int = 11, normC: float | None = None):
+    """O2 for square sparse C of bandwidth b: sigma_min(C - z I) by block
+    inverse subspace iteration on (A^* A)^{-1}, A = C - z I, with A factored
+    once per point by LAPACK's banded LU with partial pivoting (zgbtrf).
+    Each step: Y = A^{-1} (A^{-*} X), Q = qr(Y), Rayleigh-Ritz by the SVD of
+    the n x block product A Q (its smallest singular value is a Ritz value,
+    an upper bound of sigma_min), X = Q V.  Stops when the smallest Ritz value
+    changes by at most tol_rel ||C|| between steps.  Returns (sigma, steps);
+    steps = -1 marks a point that hit max_iter."""
+    import scipy.sparse as sp
+    from scipy.linalg import lapack
+    if m != n:
+        raise ValueError("sigma_min_sparse_lu: square C only")
+    A0 = sp.csr_matrix((np.asarray(vals, dtype=np.complex128), np.asarray(colind), np.asarray(rowptr)),
+                       shape=(m, n)).tocoo()
+    off = A0.col.astype(np.int64) - A0.row.astype(np.int64)
+    kl = int(max(0, -off.min())) if off.size else 0
+    ku = int(max(0, off.max())) if off.size else 0
+    if normC is None:
+        normC = norm2_sparse(m, n, rowptr, colind, vals)
+    zs = np.asarray(zs, dtype=np.complex128).reshape(-1)
+    out = np.empty(zs.size)
+    steps = np.empty(zs.size, dtype=np.int64)
+    rng = np.random.default_rng(seed)
+    X0 = rng.standard_normal((n, block)) + 1j * rng.standard_normal((n, block))
+    X0, _ = np.linalg.qr(X0)
+    Acsr = sp.csr_matrix((np.asarray(vals, dtype=np.complex128), np.asarray(colind), np.asarray(rowptr)),
+                         shape=(m, n))
+    eye = sp.identity(n, dtype=np.complex128, format="csr")
+    for q, z in enumerate(zs):
+        Az = (Acsr - z * eye).tocoo()
+        ab = np.zeros((2 * kl + ku + 1, n), dtype=np.complex128, order="F")
+        ab[kl + ku + Az.row - Az.col, Az.col] = Az.data
+        lu, piv, info = lapack.zgbtrf(ab, kl, ku)
+        if info != 0:
+            raise RuntimeError("oracle O2: zgbtrf info=%d" % info)
+        Azcsr = Az.tocsr()
+        X = X0.copy()
+        prev = np.inf
+        sig = np.inf
+        for it in range(max_iter):
+            W, info1 = lapack.zgbtrs(lu, kl, ku, X, piv, trans=2)
+            Y, info2 = lapack.zgbtrs(lu, kl, ku, W, piv, trans=0)
+            if info1 or info2:
+                raise RuntimeError("oracle O2: zgbtrs failed")
+            Q, _ = np.linalg.qr(Y)
+            B = Azcsr @ Q
+            _, s, Vh = np.linalg.svd(B, full_matrices=False)
+            X = Q @ Vh.conj().T[:, ::-1]
+            sig = float(s[-1])
+            if abs(prev - sig) <= tol_rel * normC:
+                break
+            prev = sig
+        else:
+            it = -1
+        out[q] = sig
+        steps[q] = it if it >= 0 else -1
+    return out, steps

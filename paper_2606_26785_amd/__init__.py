@@ -51,7 +51,7 @@ class ps_params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("eta_abs", ctypes.c_double), ("rho_small", ctypes.c_double),
                 ("profile", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("tol_abs", ctypes.c_double), ("esc_iters", ctypes.c_int32),
-                ("cert_recycled", ctypes.c_int32), ("lipschitz", ctypes.c_int32)]
+                ("cert_recycled", ctypes.c_int32), ("reg_base", ctypes.c_double), ("lipschitz", ctypes.c_int32)]
 
 
 class ps_stats(ctypes.Structure):
@@ -106,6 +106,10 @@ def load():
     lib.ps_debug_apply.restype = ctypes.c_int
     lib.ps_debug_precond.argtypes = [P, ctypes.c_double, ctypes.c_double, P, P]
     lib.ps_debug_precond.restype = ctypes.c_int
+    lib.ps_debug_twolevel.argtypes = [P] + [ctypes.c_double] * 4 + [P, P, P, P, P]
+    lib.ps_debug_twolevel.restype = ctypes.c_int
+    lib.ps_debug_site.argtypes = [P, P, P]
+    lib.ps_debug_site.restype = ctypes.c_int
     lib.ps_debug_norm.argtypes = [P]
     lib.ps_debug_norm.restype = ctypes.c_double
     _lib = lib
@@ -278,3 +282,23 @@ def debug_precond(mat: Matrix, z: complex):
     _check(load().ps_debug_precond(mat.handle, float(np.real(z)), float(np.imag(z)), _ptr(F), _ptr(g)),
            "ps_debug_precond")
     return F, float(g[0])
+
+
+def debug_twolevel(mat: Matrix, zdag: complex, z: complex, W: np.ndarray):
+    """(Y = K_Ebar^{-1} W, Ebar, Lambda_bar, iterations, d, gamma) of the
+    two-level preconditioner built at a site z_dag and refined at z (test hook)."""
+    m, n = mat.shape
+    W = np.asfortranarray(W, dtype=np.complex128)
+    r = W.shape[1]
+    Y = np.empty((n, r), dtype=np.complex128, order="F")
+    E = np.empty((n, r), dtype=np.complex128, order="F")
+    lam = np.empty(r)
+    it = np.zeros(1, dtype=np.int32)
+    lib = load()
+    _check(lib.ps_debug_twolevel(mat.handle, float(np.real(zdag)), float(np.imag(zdag)), float(np.real(z)),
+                                 float(np.imag(z)), _ptr(W), _ptr(Y), _ptr(E), _ptr(lam), _ptr(it)),
+           "ps_debug_twolevel")
+    d = np.zeros(1)
+    g = np.zeros(1)
+    _check(lib.ps_debug_site(mat.handle, _ptr(d), _ptr(g)), "ps_debug_site")
+    return Y, E, lam, int(it[0]), float(d[0]), float(g[0])

@@ -76,6 +76,12 @@ struct Operator {
     DBuf<int32_t> ci, ciH;
     DBuf<zd> v, vH;
     double normC = 0.0;                 // ||C||_2 estimate (power iteration, x1.01)
+    // colour-ordered pattern for the incomplete LU base preconditioner (square CSR)
+    DBuf<int64_t> sp_rp, sp_src, sp_diag, sp_rpT, sp_mapT;
+    DBuf<int32_t> sp_ci, sp_ciT;
+    DBuf<int> sp_perm;
+    std::vector<int64_t> sp_cptr;
+    SparsePattern spat;
 };
 
 struct ps_gridh {
@@ -193,6 +199,64 @@ struct Engine {
                int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
                double beta, int upper = 0, int tri = 0, const int* gmap = nullptr, int cw = 0);
 
+    // ---- two-level preconditioner (Sec. 3, eq. (twolevel), Alg. 4, Alg. 5)
+    // Each preconditioner site (slot) carries a recycled projection subspace
+    // Vbar (n x KB, newest block first, so that its leading blocks span the
+    // most recent refinements as the QL form of Alg. 2 does) and the cached
+    // R factors of Mbar(z) Vbar = (C - z S) F^{-1} Vbar and of the residual
+    // blocks, so that recyProj is the same per-point Rayleigh-Ritz-SVD as
+    // recySing.  The projection block size equals r.
+    bool two_level = false;
+    int KB = 0;                                  // projection capacity (kbar_max)
+    DBuf<zd> pV, pE, pW1, pW3, pW4, pW5, pW6, pT; // per slot; pE = F^{-1} Vbar
+    DBuf<zd> pRA, pRres;                         // per slot: (2 KB)^2, (5 KB)^2
+    DBuf<zdd> pgdd;                              // per slot Gram workspace (5 KB)^2
+    DBuf<int> d_pk, d_nzp;                       // per slot: current kbar (index NS: empty); zero pivots
+    std::vector<int> pk;
+    std::vector<double> slot_lamn;               // lambda_bar_n^dagger of the site
+    std::vector<double> slot_dreg;               // regularisation shift of the site
+    // per tile
+    DBuf<zd> tE, tX0, tCoef, Tp, pG;             // Ebar (n x r), saved start block, Ebar^* W, temp, recyProj G
+    DBuf<double> tLam, pj_xi, pj_res, pj_nrm;
+    DBuf<uint8_t> pj_acc;
+    DBuf<int> pj_slot, d_listA, d_listB, d_tslot;
+    DBuf<zd> pj_z;
+    std::vector<char> phase;                     // 1: projection LOBPCG on Mbar(z) running
+    std::vector<char> use2l;                     // singular LOBPCG uses K_Ebar
+    std::vector<double> lob_sv;                  // per tile r Ritz values of the last step
+    std::vector<double> tlam_h;                  // per tile Lambda_bar (host copy)
+    void finv_apply(const std::vector<int>& L, int trans, const zd* X, int64_t xs, int64_t ldx, zd* Y, int64_t ys,
+                    int64_t ldy);
+    // C(z) X (or C(z)^* X) for singular-phase tiles, Mbar(z) X = C(z) F^{-1} X
+    // (or Mbar(z)^* X = F^{-*} C(z)^* X) for projection-phase tiles
+    void op_apply(bool herm, const std::vector<int>& L, const zd* X, int64_t xs, int64_t ldx, zd* Y, int64_t ys,
+                  int64_t ldy, int w);
+    void twolevel_add(const std::vector<int>& L, const zd* W, int64_t ws, zd* Y, int64_t ys);
+    double tbar_norm(int slot, zd z) const;      // (sqrt(lambda_n^dagger) + gamma |z - z_dag|)^2
+    int find_slot2(zd z) const;                  // the rule of eq. (tauRecycle), upper part
+    void proj_reset(int slot);
+    void proj_refresh(const std::vector<int>& slots);
+    // updateRecy (Alg. 2) on the projection store of `slot` with the block
+    // X = S[:, 0:r] of tile t and r_breve leading columns in the omega test
+    void proj_update(const std::vector<int>& slots, const std::vector<int>& tiles, const std::vector<int>& rbrev);
+    // recyProj (Alg. 4) for the tiles of L at their sites: accepted tiles get
+    // Ebar and Lambda_bar; acc[i] = 1 when eq. (tolTz) holds
+    void recy_proj(const std::vector<int>& L, std::vector<char>& acc);
+    void upload_pk();
+    // sparse sites: incomplete LU values per slot, site points, work blocks
+    DBuf<zd> Slu, Svec, pS, d_slotz, Tq;
+    DBuf<int> d_listC;
+    DBuf<int> d_nfloor;
+    int64_t ilu_floors = 0;
+    void build_sparse_pattern();        // colouring and patterns (host, once per handle)
+    std::vector<int> build_sparse_sites(const std::vector<zd>& sites, const std::vector<int>& slots);
+    bool site_at(int t) const;                   // the tile's site was built at its current point
+    // regularised base sites (precond = 2): N(z_dag) + (reg_base (||C|| + |z_dag|))^2 I
+    std::vector<int> build_regularized(const std::vector<zd>& sites);
+    // lower part of eq. (tauRecycle) failed: a new site at each tile's point,
+    // whose projection refinement then runs (phase 1); fl gets the rebuild flag
+    void rebuild_here(const std::vector<int>& tl, std::vector<uint8_t>& fl);
+
     KProf prof;
     int zgemm_cls = 1;        // profiling class of zgemm launches (3 inside factorizations)
     ps_stats stats{};
@@ -228,7 +292,7 @@ struct Engine {
                         int64_t rows, int cols, const BlockList* against, int against_max, uint64_t seed);
     // nzero (optional, per tile): number of pivots the Cholesky treated as zero
     void r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul, int cfixed,
-                  zd* R, int64_t strideR, int ldR, int* nzero = nullptr);
+                  zd* R, int64_t strideR, int ldR, int* nzero = nullptr, zdd* gbuf = nullptr);
 
     // ---- algorithm steps
     // LOBPCG-SVD as a per-tile state machine: lob_start runs the first
@@ -258,6 +322,8 @@ struct Engine {
 };
 
 BlockList bl_empty(int64_t rows);
+// the last block added to L is indexed through imap (array index imap[tile])
+void bl_map(BlockList& L, const int* imap);
 void bl_add(BlockList& L, const zd* ptr, int64_t stride, int64_t ld, int ncols, const int* dims, int mul,
             int64_t brows = 0, const int* coff = nullptr, int coffmul = 0);
 void launch_gather(const int* list, int nt, const int* srcidx, const zd* src, int64_t sstride, zd* dst,

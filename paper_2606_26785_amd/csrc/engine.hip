@@ -17,6 +17,7 @@ BlockList bl_empty(int64_t rows)
     L.rows = rows;
     return L;
 }
+void bl_map(BlockList& L, const int* imap) { L.imap[L.nb - 1] = imap; }
 void bl_add(BlockList& L, const zd* ptr, int64_t stride, int64_t ld, int ncols, const int* dims, int mul,
             int64_t brows, const int* coff, int coffmul)
 {
@@ -249,17 +250,18 @@ void Engine::colnorm2(const int* dlist, int nt, const BlockList& A, int camax, d
 // double-double accuracy, so R equals the R factor of a backward-stable QR
 // of A up to rounding of R itself.
 void Engine::r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul,
-                      int cfixed, zd* R, int64_t strideR, int ldR, int* nzero)
+                      int cfixed, zd* R, int64_t strideR, int ldR, int* nzero, zdd* gbuf)
 {
     if (nt <= 0) return;
-    gram(dlist, nt, A, A, cmax, cmax, gdd.p, (int64_t)cmax * cmax, cmax, true, true);
+    zdd* gb = gbuf ? gbuf : gdd.p;
+    gram(dlist, nt, A, A, cmax, cmax, gb, (int64_t)cmax * cmax, cmax, true, true);
     CholArgs c;
     memset(&c, 0, sizeof(c));
     c.list = dlist;
     c.cdim = cdims;
     c.cmul = cmul;
     c.c = cfixed > 0 ? cfixed : cmax;   // with cdims: the maximum, used to size the launch
-    c.G = gdd.p;
+    c.G = gb;
     c.strideG = (int64_t)cmax * cmax;
     c.ldG = cmax;
     c.R = R;
@@ -360,6 +362,7 @@ void Engine::apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xst
         a.nshift = op.n;
         a.part = apply_ws.p;
         int64_t N = (int64_t)nt * w;
+        if (apply_ws.n < (size_t)a.m * N) throw DeviceError("operator-apply workspace too small");
         a.splitk = (int)std::max<int64_t>(1, (int64_t)(apply_ws.n / ((size_t)a.m * N)));
         int pi = prof.begin(st, 0, 8.0 * a.m * a.K * N, 16.0 * ((double)a.m * a.K + (double)a.K * N + (double)a.m * N));
         launch_dense_apply(a, st);
@@ -406,6 +409,10 @@ void Engine::create(const ps_matrix_desc* d, const ps_params* p, hipStream_t s)
                                        (size_t)P.k_max * P.k_max + 7 * P.r * P.r + 2 * P.r * P.k_max) * sizeof(zd);
         if (need + 4096 > (size_t)small_kernels_max_lds())
             throw InvalidArg("k_max too large for this device's LDS per workgroup");
+        // recyProj runs the same kernel on the projection store (kbar_max)
+        const int pc = P.precond < 0 ? (d->kind == PS_DENSE ? 1 : (d->m == d->n ? 2 : 0)) : P.precond;
+        if (pc == 2 && (size_t)2 * P.kbar_max * P.kbar_max * sizeof(zd) + 4096 > (size_t)small_kernels_max_lds())
+            throw InvalidArg("kbar_max too large for this device's LDS per workgroup");
     }
     if (d->kind == PS_DENSE) {
         size_t cnt = (size_t)d->m * d->n;
@@ -462,13 +469,15 @@ void Engine::create(const ps_matrix_desc* d, const ps_params* p, hipStream_t s)
     m = op.m;
     r = P.r;
     K = P.k_max;
-    if (P.precond < 0) P.precond = (op.kind == PS_DENSE) ? 1 : 0;
-    if (P.precond > 0 && op.kind != PS_DENSE)
-        throw InvalidArg("precond = 1 needs a dense matrix in this version");
+    if (P.precond < 0) P.precond = (op.kind == PS_DENSE) ? 1 : (m == n ? 2 : 0);
+    if (P.precond > 0 && op.kind != PS_DENSE && m != n)
+        throw InvalidArg("the sparse base preconditioner needs a square matrix");
     use_prec = P.precond > 0;
+    two_level = P.precond == 2;
+    if (use_prec && op.kind != PS_DENSE) build_sparse_pattern();
     size_for(1);
     estimate_norm();
-    if (use_prec) {
+    if (use_prec && op.kind == PS_DENSE) {
         // C^* C once, for N(z) = C^*C - conj(z) S^*C - z C^*S + |z|^2 I
         CtC.alloc((size_t)n * n);
         zgemm(nullptr, 1, n, n, m, op.A.p, m, 0, 1, op.A.p, m, 0, CtC.p, n, 0, 1.0, 0.0);
@@ -547,7 +556,9 @@ void Engine::size_for(int tiles)
     gram_ws_bytes = std::max<size_t>((size_t)256 << 20, t * (size_t)cmax * cmax * sizeof(zdd) * 2);
     gram_ws.alloc(gram_ws_bytes);
     const size_t maxw = (size_t)std::max(r, P.rbar);
-    apply_ws.alloc((size_t)std::max(m, n) * std::max<size_t>(t * maxw, 64) * 4);
+    const size_t kbw = (size_t)32 * std::max(P.kbar_max, 1);      // projection-store refresh: 32 sites x KB columns
+    if (op.kind == PS_DENSE)
+        apply_ws.alloc((size_t)std::max(m, n) * std::max<size_t>(std::max<size_t>(t * maxw, 64), kbw) * 4);
     norm_ws.alloc(std::max<size_t>(1 << 20, t * 3 * r * 256));
     {
         std::vector<int> cv(3 * t);
@@ -556,20 +567,67 @@ void Engine::size_for(int tiles)
     }
     NBLD = 0;
     NS = 0;
-    if (use_prec) {
+    if (use_prec && op.kind == PS_DENSE) {
         const size_t nn = (size_t)n * n;
         // staging for up to 32 simultaneous constructions; the site pool holds
         // one slot per tile plus the staging count (so a free slot always
-        // exists), within 96 GB
+        // exists), within 128 GB
         NBLD = 32;
-        const size_t cap = std::max<size_t>(2, ((size_t)96 << 30) / (nn * sizeof(zd)));
+        const size_t cap = std::max<size_t>(2, ((size_t)128 << 30) / (nn * sizeof(zd)));
         NS = (int)std::min<size_t>(t + NBLD, cap);
+        // with the two-level preconditioner a site serves a whole region
+        if (two_level) NS = std::min(NS, 160);
         PN.alloc(NBLD * nn); Fb.alloc(NBLD * nn); Finv.alloc((size_t)NS * nn);
         Dinv.alloc(NBLD * n * PRE_NB); T1p.alloc(NBLD * n * PRE_NB); T2p.alloc(NBLD * n * PRE_OB); pvec.alloc(NBLD * 2 * n); d_zdag.alloc(NBLD);
         d_shift.alloc(NBLD); d_notpd.alloc(NBLD);
         zgemm_ws.alloc(std::max<size_t>((size_t)32 << 20, t * (size_t)n * r * 16));
+    } else if (use_prec) {
+        // incomplete LU sites: values, power-iteration vectors, solve work;
+        // the projection stores (8 n x kbar blocks per site) bound the count
+        NBLD = 8;
+        const double per = 16.0 * ((double)op.spat.nnz + 4.0 * n + (two_level ? 9.0 : 1.0) * n * P.kbar_max);
+        NS = (int)std::max(2.0, std::min((double)t + NBLD, std::min(64.0, 24e9 / per)));
+        Slu.alloc((size_t)NS * op.spat.nnz);
+        Svec.alloc((size_t)NS * 4 * n);
+        pS.alloc((size_t)NS * n * std::max(P.kbar_max, 1));
+        d_slotz.alloc(NS);
+        d_nfloor.alloc(1);
+        Tq.alloc(t * n * r);
+        d_listC.alloc(std::max<size_t>(t, NS));
+        std::vector<zd> z0((size_t)NS, zmake(0.0, 0.0));
+        HIPCHK(hipMemcpy(d_slotz.p, z0.data(), sizeof(zd) * NS, hipMemcpyHostToDevice));
     }
-    nrm2.alloc(std::max<size_t>(t, NBLD) * 3 * r);
+    nrm2.alloc(std::max<size_t>(std::max<size_t>(t, NBLD), (size_t)NS + 1) * 3 * r);
+    if (use_prec) {
+        Tp.alloc(t * std::max(m, n) * r);
+        d_tslot.alloc(std::max<size_t>(t, (size_t)NS + 1));
+    }
+    if (two_level) {
+        KB = P.kbar_max;
+        const size_t ns = (size_t)NS, snk = (size_t)n * KB, smk = (size_t)m * KB;
+        pV.alloc(ns * snk); pE.alloc(ns * snk); pW3.alloc(ns * snk); pW4.alloc(ns * snk);
+        pW5.alloc(ns * snk); pW6.alloc(ns * snk); pW1.alloc(ns * smk); pT.alloc(ns * smk);
+        pRA.alloc(ns * 4 * KB * KB); pRres.alloc(ns * 25 * KB * KB); pgdd.alloc((ns + 1) * 25 * KB * KB);
+        d_pk.alloc(ns + 1); d_nzp.alloc(ns + 1);
+        pk.assign(ns, 0);
+        tE.alloc(t * n * r); tX0.alloc(t * n * r); tCoef.alloc(t * r * r);
+        Tp.alloc(t * std::max(m, n) * r); pG.alloc(t * KB * r);
+        tLam.alloc(t * r); pj_xi.alloc(t * r); pj_res.alloc(t * r); pj_nrm.alloc(t); pj_acc.alloc(t);
+        pj_slot.alloc(t); pj_z.alloc(t); d_listA.alloc(t); d_listB.alloc(std::max(t, ns));
+        d_tslot.alloc(std::max(t, ns + 1));
+        phase.assign(t, 0);
+        use2l.assign(t, 0);
+        lob_sv.assign(t * r, 0.0);
+        tlam_h.assign(t * r, 0.0);
+        upload_pk();
+    } else {
+        phase.assign(t, 0);
+        use2l.assign(t, 0);
+        lob_sv.assign(t * r, 0.0);
+        d_listA.alloc(t); d_listB.alloc(t);
+    }
+    slot_lamn.assign(NS, 1.0);
+    slot_dreg.assign(NS, 0.0);
     slot_z.assign(NS, zmake(0.0, 0.0));
     slot_gam.assign(NS, 0.0);
     slot_ref.assign(NS, 0);
@@ -579,7 +637,8 @@ void Engine::size_for(int tiles)
     tile_slot.assign(t, -1);
     d_listI.alloc(t);
     usek.assign(t, 1);
-    h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r)); h_nrm2.alloc(std::max<size_t>(t, NBLD) * 3 * r);
+    h_acc.alloc(J); h_xi.alloc(std::max<size_t>(J, t * 3 * r));
+    h_nrm2.alloc(std::max<size_t>(std::max<size_t>(t, NBLD), (size_t)NS + 1) * 3 * r);
     h_small.alloc(std::max<size_t>(t, NBLD) * 4 + 8); h_C.alloc(t * K * r + 8); h_list.alloc(t + 1); h_z.alloc(t + J);
 }
 

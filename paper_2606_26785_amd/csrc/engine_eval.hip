@@ -289,6 +289,18 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     std::vector<char> cert_pend(T, 0), cert_ok(T, 0);
     std::vector<double> cert_mu(T, 0.0), cert_xi(T, 0.0);
     std::vector<int64_t> cert_since(T, 0);
+    // a refinement (re)starts on tile t: reset the LOBPCG bookkeeping
+    auto begin_refinement = [&](int t) {
+        state[t] = 1;
+        cert_pend[t] = 0;
+        cert_ok[t] = 0;
+        esc_at[t] = P.esc_iters;
+        site_exact[t] = 0;
+        stag[t] = 0;
+        cert_next[t] = 0;
+        cert_fail[t] = 0;
+        lob_prev[t] = INFINITY;
+    };
     auto run_tiles = [&]() {
     pending.clear();
     std::fill(cert_pend.begin(), cert_pend.end(), 0);
@@ -529,7 +541,8 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 while (!pend.empty()) {
                     std::vector<int> rest;
                     for (int t : pend) {
-                        int s = find_slot(zs[tiles[t].order[tiles[t].cursor]]);
+                        const zd zt = zs[tiles[t].order[tiles[t].cursor]];
+                        int s = two_level ? find_slot2(zt) : find_slot(zt);
                         if (s >= 0) {
                             tile_slot[t] = s;
                             slot_ref[s]++;
@@ -556,7 +569,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                         sest.push_back(est[t]);
                         fl[tiles[t].order[tiles[t].cursor]] |= PS_FLAG_REBUILD;
                     }
-                    std::vector<int> got = build_precond(sites);
+                    std::vector<int> got = two_level ? build_regularized(sites) : build_precond(sites);
                     bool failed = sites.empty();
                     for (int s : got) failed |= (s < 0);
                     if (failed) {
@@ -581,19 +594,42 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             for (int t : R) h_zt[t] = zs[tiles[t].order[tiles[t].cursor]];
             for (int t = 0; t < T; ++t) h_z[t] = h_zt[t];
             h2d(d_z.p, h_z.p, sizeof(zd) * T);
+            // Alg. 5 with the two-level preconditioner: recyProj at the
+            // tile's site gives Ebar and Lambda_bar when eq. (tolTz) holds;
+            // otherwise the projection LOBPCG on Mbar(z) runs first (phase
+            // 1), and the singular start block waits in tX0
+            if (two_level) {
+                std::vector<int> Lp;
+                for (int t : R) {
+                    phase[t] = 0;
+                    use2l[t] = 0;
+                    if (usek[t] && tile_slot[t] >= 0) Lp.push_back(t);
+                }
+                if (!Lp.empty()) {
+                    auto tq0 = now();
+                    upload_list(Lp, d_listI);
+                    launch_copy_cols(d_listI.p, (int)Lp.size(), S.p, sS, n, tX0.p, (int64_t)n * r, n, n, r, st);
+                    std::vector<char> acc;
+                    recy_proj(Lp, acc);
+                    std::vector<int> rebuild;
+                    for (size_t i = 0; i < Lp.size(); ++i) {
+                        const int t = Lp[i];
+                        if (acc[i]) {
+                            // lower part of eq. (tauRecycle)
+                            if (tlam_h[(size_t)t * r + r - 1] < P.tau_min && !site_at(t)) rebuild.push_back(t);
+                            else use2l[t] = 1;
+                        } else {
+                            phase[t] = 1;
+                            stats.proj_refined++;
+                        }
+                    }
+                    rebuild_here(rebuild, fl);
+                    stats.t_precond_ms += ms(tq0, now());
+                }
+            }
             step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
             lob_start(R, step_seed);
-            for (int t : R) {
-                state[t] = 1;
-                cert_pend[t] = 0;
-                cert_ok[t] = 0;
-                esc_at[t] = P.esc_iters;
-                site_exact[t] = 0;
-                stag[t] = 0;
-                cert_next[t] = 0;
-                cert_fail[t] = 0;
-                lob_prev[t] = INFINITY;
-            }
+            for (int t : R) begin_refinement(t);
         }
         // ---- C. one LOBPCG iteration for every running tile
         std::vector<int> run;
@@ -623,7 +659,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         // cannot resolve them) get an exact site N(z) + delta I at their own
         // point instead.  slack bounds the rounding of forming N(z) and of the
         // Cholesky factorization.
-        if (use_prec && P.esc_iters > 0) {
+        if (use_prec && P.esc_iters > 0 && op.kind == PS_DENSE) {
             std::vector<char> isfin(T, 0);
             for (int t : fin) isfin[t] = 1;
             std::vector<zd> fsites;
@@ -631,6 +667,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             std::vector<int> fown, fkind;
             for (int t : run) {
                 if (isfin[t]) continue;
+                if (two_level && phase[t]) continue;
                 if (cert_pend[t]) continue;
                 const zd z = h_zt[t];
                 const double xi = lob_xi[t];
@@ -719,6 +756,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                         slot_ref[sl]++;
                         usek[t] = 1;
                         if (fkind[i] != 3) site_exact[t] = 1;
+                        use2l[t] = 0;   // the projection vectors belong to the previous site
                     } else {
                         slot_valid[sl] = 0;
                     }
@@ -749,6 +787,67 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         }
         auto t3 = now();
         t_lob += ms(t1, t3) - 0.0 * ms(t1, t2);
+        // ---- D0. finished projection refinements (Alg. 5): Ebar = F^{-1}
+        // Xbar, Lambda_bar = Sigma_bar^2, updateRecy on the site's projection
+        // store with the r_breve columns whose sigma_bar^2 <= tau_min, the
+        // lower part of eq. (tauRecycle) (a new site at z and the projection
+        // refinement again when lambda_bar_rbar < tau_min), then the singular
+        // LOBPCG from the saved start block with K_Ebar
+        if (two_level && !fin.empty()) {
+            std::vector<int> pf, fin2, okv2;
+            for (size_t i = 0; i < fin.size(); ++i) {
+                if (phase[fin[i]]) pf.push_back(fin[i]);
+                else { fin2.push_back(fin[i]); okv2.push_back(okv[i]); }
+            }
+            if (!pf.empty()) {
+                auto tq0 = now();
+                fin.swap(fin2);
+                okv.swap(okv2);
+                finv_apply(pf, 0, S.p, sS, n, tE.p, (int64_t)n * r, n);
+                for (int t : pf) fl[tiles[t].order[tiles[t].cursor]] |= PS_FLAG_PROJ_REFINED;
+                std::vector<int> us, ut, ub, rebuild, go;
+                std::vector<char> seen(NS, 0);
+                for (int t : pf) {
+                    int rb = 0;
+                    for (int j = 0; j < r; ++j) {
+                        const double l = lob_sv[(size_t)t * r + j] * lob_sv[(size_t)t * r + j];
+                        tlam_h[(size_t)t * r + j] = l;
+                        if (l <= P.tau_min) rb = j + 1;
+                    }
+                    const int sl = tile_slot[t];
+                    if (rb > 0 && !seen[sl]) {
+                        seen[sl] = 1;
+                        us.push_back(sl);
+                        ut.push_back(t);
+                        ub.push_back(rb);
+                    }
+                    if (tlam_h[(size_t)t * r + r - 1] < P.tau_min && !site_at(t)) rebuild.push_back(t);
+                    else go.push_back(t);
+                }
+                h2d(tLam.p, tlam_h.data(), sizeof(double) * T * r);
+                proj_update(us, ut, ub);
+                rebuild_here(rebuild, fl);
+                std::vector<int> again;
+                for (int t : rebuild) {
+                    if (phase[t]) again.push_back(t);
+                    else go.push_back(t);
+                }
+                for (int t : go) {
+                    phase[t] = 0;
+                    use2l[t] = 1;
+                }
+                if (!go.empty()) {
+                    upload_list(go, d_list2);
+                    launch_copy_cols(d_list2.p, (int)go.size(), tX0.p, (int64_t)n * r, n, S.p, sS, n, n, r, st);
+                }
+                std::vector<int> restart(again);
+                restart.insert(restart.end(), go.begin(), go.end());
+                step_seed = step_seed * 6364136223846793005ull + 1442695040888963407ull;
+                lob_start(restart, step_seed);
+                for (int t : restart) begin_refinement(t);
+                stats.t_precond_ms += ms(tq0, now());
+            }
+        }
         // ---- D. finished tiles: record sigma and gamma = x^* C(z) x of the
         // first Ritz vector, update their recycled store
         if (!fin.empty()) {

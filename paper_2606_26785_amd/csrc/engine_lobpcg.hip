@@ -21,7 +21,7 @@ void Engine::lob_start(const std::vector<int>& L, uint64_t seed)
     const int64_t sS = (int64_t)n * 3 * r, sC = (int64_t)m * 3 * r;
     const int r3 = 3 * r;
     orthonormalize(L, d_list.p, S.p, sS, n, n, r, nullptr, 0, seed);
-    apply(false, d_list.p, nt, S.p, sS, n, CS.p, sC, m, r, d_z.p);
+    op_apply(false, L, S.p, sS, n, CS.p, sC, m, r);
     BlockList Lcx = bl_empty(m);
     bl_add(Lcx, CS.p, sC, m, r, nullptr, 0);
     r_factor(d_list.p, nt, Lcx, r, nullptr, 0, r, Rsm.p, (int64_t)9 * r * r, r3);
@@ -49,7 +49,7 @@ void Engine::lob_start(const std::vector<int>& L, uint64_t seed)
     gemm_ts(d_list.p, nt, Lcx, r, GX.p, (int64_t)9 * r * r, r3, nullptr, 0, r, CSn.p, sC, m, m, 1.0, 0.0);
     launch_copy_cols(d_list.p, nt, Sn.p, sS, n, S.p, sS, n, n, r, st);
     launch_copy_cols(d_list.p, nt, CSn.p, sC, m, CS.p, sC, m, m, r, st);
-    apply(true, d_list.p, nt, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r, d_z.p);
+    op_apply(true, L, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r);
     launch_resid_xi(d_list.p, nt, Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
     for (int t : L) lob_it[t] = 0;
 }
@@ -62,7 +62,7 @@ std::vector<double> Engine::explicit_rq(const std::vector<int>& L)
     const int r3 = 3 * r;
     upload_list(L, d_list2);
     const int nt = (int)L.size();
-    apply(false, d_list2.p, nt, S.p, sS, n, CS.p, sC, m, r, d_z.p);
+    op_apply(false, L, S.p, sS, n, CS.p, sC, m, r);
     BlockList Lx = bl_empty(n);
     bl_add(Lx, S.p, sS, n, 1, nullptr, 0);
     BlockList Lcx = bl_empty(m);
@@ -105,13 +105,21 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
         h2d(d_cdimt.p, hc, sizeof(int) * T);
         h2d(d_pcols.p, hc + T, sizeof(int) * T);
     }
-    // W <- K^{-1} W into S[:, r:2r]
+    // W <- K^{-1} W into S[:, r:2r]: K = F^* F of the tile's site, plus the
+    // coarse term Ebar Lambda_bar^{-1} Ebar^* W of eq. (twolevel) when the
+    // tile has projection vectors; projection-phase tiles run with K = I
     if (use_prec) {
-        std::vector<int> Lk, Li;
-        for (int t : L) (usek[t] ? Lk : Li).push_back(t);
+        std::vector<int> Lk, Li, L2;
+        for (int t : L) {
+            const bool pre = usek[t] && !(two_level && phase[t]);
+            (pre ? Lk : Li).push_back(t);
+            if (pre && two_level && use2l[t]) L2.push_back(t);
+            if (two_level && phase[t]) stats.proj_iters++;
+        }
         stats.precond_iters += (int64_t)Lk.size();
         upload_list(Li, d_listI);
         precond_apply(Lk, Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
+        twolevel_add(L2, Wres.p, (int64_t)n * r, S.p + (size_t)n * r, sS);
         launch_copy_cols(d_listI.p, (int)Li.size(), Wres.p, (int64_t)n * r, n, S.p + (size_t)n * r, sS, n, n, r,
                          st);
     } else {
@@ -122,7 +130,7 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
     bl_add(Lxp, S.p, sS, n, r, nullptr, 0);
     bl_add(Lxp, S.p + (size_t)2 * n * r, sS, n, 0, d_pcols.p, 1);
     orthonormalize(L, d_list.p, S.p + (size_t)n * r, sS, n, n, r, &Lxp, 2 * r, seed);
-    apply(false, d_list.p, nt, S.p + (size_t)n * r, sS, n, CS.p + (size_t)m * r, sC, m, r, d_z.p);
+    op_apply(false, L, S.p + (size_t)n * r, sS, n, CS.p + (size_t)m * r, sC, m, r);
     BlockList Lcs = bl_empty(m);
     bl_add(Lcs, CS.p, sC, m, 0, d_cdimt.p, 1);
     r_factor(d_list.p, nt, Lcs, r3, d_cdimt.p, 1, 0, Rsm.p, (int64_t)9 * r * r, r3);
@@ -158,11 +166,11 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
     launch_copy_cols(d_list.p, nt, CSn.p, sC, m, CS.p, sC, m, m, r, st);
     launch_copy_cols(d_list.p, nt, CSn.p + (size_t)m * r, sC, m, CS.p + (size_t)2 * m * r, sC, m, m, r, st);
     for (int t : L) lob_it[t]++;
-    auto residual = [&](const int* dl, int k) {
-        apply(true, dl, k, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r, d_z.p);
-        launch_resid_xi(dl, k, Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
+    auto residual = [&](const std::vector<int>& Lh, const int* dl) {
+        op_apply(true, Lh, CS.p, sC, m, Wres.p, (int64_t)n * r, n, r);
+        launch_resid_xi(dl, (int)Lh.size(), Wres.p, (int64_t)n * r, n, S.p, sS, n, xi.p, r3, n, r, st);
     };
-    residual(d_list.p, nt);
+    residual(L, d_list.p);
     BlockList Lw = bl_empty(n);
     bl_add(Lw, Wres.p, (int64_t)n * r, n, r, nullptr, 0);
     BlockList Lx = bl_empty(n);
@@ -209,18 +217,35 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
         bool flo = w0 <= floor_c * nz * nz * EPSM_L && w0 <= P.tol_abs * nC * x0;
         return lin || flo || x0 <= P.eta_abs * nC;
     };
+    // projection phase (LOBPCG-SVD on Mbar(z) with r_v = r): every Ritz pair
+    // meets the relaxed test of eq. (tolTz), ||W_j|| <= eta_proj ||Tbar(z)||
+    auto passes_proj = [&](int t) {
+        const double nT = tbar_norm(tile_slot[t], h_zt[t]);
+        for (int j = 0; j < r; ++j)
+            if (!(sqrt(std::max(0.0, h_nrm2[(size_t)t * r3 + j])) <= P.eta_proj * nT)) return false;
+        return true;
+    };
     std::vector<int> cand;
-    for (int t : L) lob_xi[t] = h_xi[(size_t)t * r3];
-    for (int t : L) if (!lob_bad[t] && passes(t, h_xi[(size_t)t * r3])) cand.push_back(t);
     std::vector<char> fin(T, 0);
+    for (int t : L) {
+        lob_xi[t] = h_xi[(size_t)t * r3];
+        for (int j = 0; j < r; ++j) lob_sv[(size_t)t * r + j] = h_xi[(size_t)t * r3 + j];
+    }
+    for (int t : L) {
+        if (two_level && phase[t]) {
+            if (!lob_bad[t] && passes_proj(t)) fin[t] = 1;
+            continue;
+        }
+        if (!lob_bad[t] && passes(t, h_xi[(size_t)t * r3])) cand.push_back(t);
+    }
     if (!cand.empty()) {
         // explicit recomputation of C(z) X before accepting (the implicit
         // updates of C X drift); the value returned for the point is the
         // Rayleigh quotient ||C(z) x_1|| / ||x_1|| of the recomputed product,
         // an upper bound of sigma_min up to the rounding of one apply
         upload_list(cand, d_list2);
-        apply(false, d_list2.p, (int)cand.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
-        residual(d_list2.p, (int)cand.size());
+        op_apply(false, cand, S.p, sS, n, CS.p, sC, m, r);
+        residual(cand, d_list2.p);
         colnorm2(d_list2.p, (int)cand.size(), Lw, r, nrm2.p, r3);
         colnorm2(d_list2.p, (int)cand.size(), Lcx, r, nrm2.p + r, r3);
         colnorm2(d_list2.p, (int)cand.size(), Lx, r, nrm2.p + 2 * r, r3);
@@ -241,11 +266,19 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
         stats.repairs += (int64_t)bad.size();
         upload_list(bad, d_list2);
         orthonormalize(bad, d_list2.p, S.p, sS, n, n, r, nullptr, 0, seed ^ 0x5bd1e995ull);
-        apply(false, d_list2.p, (int)bad.size(), S.p, sS, n, CS.p, sC, m, r, d_z.p);
-        residual(d_list2.p, (int)bad.size());
+        op_apply(false, bad, S.p, sS, n, CS.p, sC, m, r);
+        residual(bad, d_list2.p);
         for (int t : bad) nop[t] = 1;
     }
+    const int proj_cap = std::min(P.max_iters, 100);
     for (int t : L) {
+        if (two_level && phase[t]) {
+            if (fin[t] || lob_it[t] >= proj_cap) {
+                done.push_back(t);
+                okv.push_back(fin[t] ? 3 : 4);
+            }
+            continue;
+        }
         if (fin[t] || lob_it[t] >= P.max_iters) {
             if (!fin[t]) lob_sigma[t] = h_xi[(size_t)t * r3];
             done.push_back(t);

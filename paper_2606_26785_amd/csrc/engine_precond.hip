@@ -93,6 +93,12 @@ int Engine::find_slot(zd z) const
 void Engine::precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, zd* Y, int64_t ys)
 {
     if (L.empty()) return;
+    if (op.kind != PS_DENSE) {
+        // K^{-1} W = (F P)^{-1} (F P)^{-*} W with each tile's incomplete LU site
+        finv_apply(L, 1, W, ws, n, Tn2.p, (int64_t)n * r, n);
+        finv_apply(L, 0, Tn2.p, (int64_t)n * r, n, Y, ys, n);
+        return;
+    }
     std::vector<int> order(L);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tile_slot[x] < tile_slot[y]; });
     std::vector<int> gs, goff, gcnt;
@@ -137,6 +143,47 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
 {
     std::vector<int> out;
     if (pd) pd->assign(sites.size(), 0);
+    if (op.kind != PS_DENSE) {
+        // sparse sites: incomplete LU of C - z_dag I (shifts and inertia
+        // tests are dense-only: a factorisation for a test is reported as
+        // not positive definite, so no certificate is taken from it)
+        if (cert_only) {
+            out.assign(sites.size(), -1);
+            return out;
+        }
+        std::vector<zd> zs_ok;
+        std::vector<int> sl_ok;
+        for (size_t i = 0; i < sites.size(); ++i) {
+            int s = -1;
+            for (int q = 0; q < NS && s < 0; ++q) if (!slot_valid[q]) s = q;
+            if (s < 0)
+                for (int q = 0; q < NS; ++q) {
+                    if (slot_ref[q] > 0) continue;
+                    if (s < 0 || slot_last[q] < slot_last[s]) s = q;
+                }
+            out.push_back(s);
+            if (s < 0) continue;
+            slot_valid[s] = 1;           // taken for this batch
+            slot_ref[s]++;
+            zs_ok.push_back(sites[i]);
+            sl_ok.push_back(s);
+        }
+        build_sparse_sites(zs_ok, sl_ok);
+        for (size_t i = 0; i < sl_ok.size(); ++i) {
+            const int s = sl_ok[i];
+            slot_ref[s]--;
+            slot_priv[s] = priv ? 1 : 0;
+            slot_z[s] = zs_ok[i];
+            slot_last[s] = ++slot_clock;
+            if (two_level) pk[s] = 0;
+            stats.rebuilds++;
+            if (priv) stats.builds_private++;
+            else stats.builds_shared++;
+            if (pd) (*pd)[i] = 1;
+        }
+        if (two_level) upload_pk();
+        return out;
+    }
     struct ClsGuard {
         int& c;
         ClsGuard(int& x) : c(x) { c = 3; }
@@ -257,6 +304,10 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
                                   hipMemcpyDeviceToDevice, st));
             slot_valid[s] = 1;
             slot_priv[s] = priv ? 1 : 0;
+            if (two_level) {
+                pk[s] = 0;            // a new site starts with an empty projection store
+                slot_lamn[s] = 1.0;
+            }
             slot_z[s] = sites[b0 + i];
             slot_gam[s] = sqrt(std::max(g2[i], 0.0));
             slot_last[s] = ++slot_clock;
@@ -266,5 +317,6 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
         }
         HIPCHK(hipStreamSynchronize(st));
     }
+    if (two_level && !cert_only) upload_pk();
     return out;
 }

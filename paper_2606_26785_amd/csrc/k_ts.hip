@@ -7,10 +7,15 @@
 
 #define NT 256
 
+// array index of block b for tile t
+__device__ __host__ inline int bl_t(const BlockList& L, int b, int t)
+{
+    return L.imap[b] ? L.imap[b][t] : t;
+}
 // column count of block b for tile t
 __device__ __host__ inline int bl_cols(const BlockList& L, int b, int t)
 {
-    return L.dims[b] ? L.dims[b][t] * L.mul[b] : L.ncols[b];
+    return L.dims[b] ? L.dims[b][bl_t(L, b, t)] * L.mul[b] : L.ncols[b];
 }
 // element (i, c) of the block list for tile t (zero beyond a block's rows)
 __device__ inline zd bl_get(const BlockList& L, int t, int64_t i, int c)
@@ -20,8 +25,9 @@ __device__ inline zd bl_get(const BlockList& L, int t, int64_t i, int c)
         if (c < nc) {
             int64_t br = L.brows[b] ? L.brows[b] : L.rows;
             if (i >= br) return zmake(0.0, 0.0);
-            int c0 = L.coff[b] ? L.coff[b][t] * L.coffmul[b] : 0;
-            return L.ptr[b][(size_t)t * L.stride[b] + i + (size_t)(c + c0) * L.ld[b]];
+            const int tb = bl_t(L, b, t);
+            int c0 = L.coff[b] ? L.coff[b][tb] * L.coffmul[b] : 0;
+            return L.ptr[b][(size_t)tb * L.stride[b] + i + (size_t)(c + c0) * L.ld[b]];
         }
         c -= nc;
     }
@@ -175,8 +181,9 @@ __global__ void __launch_bounds__(NT) k_gemm_ts(GemmTSArgs a)
         int ncb = bl_cols(a.A, b, tile);
         int64_t br = a.A.brows[b] ? a.A.brows[b] : a.A.rows;
         if (row < br) {
-            int cof = a.A.coff[b] ? a.A.coff[b][tile] * a.A.coffmul[b] : 0;
-            const zd* p = a.A.ptr[b] + (size_t)tile * a.A.stride[b] + (size_t)cof * a.A.ld[b] + row;
+            const int tb = bl_t(a.A, b, tile);
+            int cof = a.A.coff[b] ? a.A.coff[b][tb] * a.A.coffmul[b] : 0;
+            const zd* p = a.A.ptr[b] + (size_t)tb * a.A.stride[b] + (size_t)cof * a.A.ld[b] + row;
             for (int c = 0; c < ncb; ++c) {
                 zd x = p[(size_t)c * a.A.ld[b]];
                 const zd* gr = Gs + (cglob + c);

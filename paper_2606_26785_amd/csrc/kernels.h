@@ -80,6 +80,8 @@ struct BlockList {
     int64_t brows[TS_MAXB];      // rows stored in block b (rows beyond read as zero; 0 = all)
     const int* coff[TS_MAXB];    // per-tile first column = coff[tile] * coffmul[b] (if non-NULL)
     int coffmul[TS_MAXB];
+    const int* imap[TS_MAXB];    // block b of tile t lives at index imap[b][t] of its array (if
+                                 // non-NULL; e.g. a preconditioner site shared by several tiles)
     int64_t rows;                // logical rows of the tall matrix
 };
 // G = A^* B (double-double accumulation when dd != 0; zdd output) or double
@@ -198,3 +200,22 @@ void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int
 void launch_chol_step(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,
                       int64_t strideD, zd* Finv, int64_t strideF, double floor_piv, int* notpd, hipStream_t s);
 void launch_zero_tiles(const int* list, int nt, zd* A, int64_t stride, int64_t count, hipStream_t s);
+
+// ---- sparse base preconditioner (k_sparse.hip) ------------------------------
+// Pattern of P (C - z I) P^T (diagonal always present, columns sorted) with P
+// the colour ordering; rows of colour c are [cptr[c], cptr[c+1]).
+struct SparsePattern {
+    int64_t n = 0, nnz = 0;
+    int ncolors = 0;
+    const int64_t* cptr = nullptr;                  // host array, ncolors + 1
+    const int64_t* rp = nullptr; const int32_t* ci = nullptr;
+    const int64_t* src = nullptr;                   // entry -> entry of C's CSR, -1 for an added diagonal
+    const int64_t* diag = nullptr;                  // row -> its diagonal entry
+    const int64_t* rpT = nullptr; const int32_t* ciT = nullptr; const int64_t* mapT = nullptr;  // transpose
+    const int* perm = nullptr;                      // permuted row -> original row
+};
+void launch_ilu(const int* list, int ns, const SparsePattern& sp, const zd* vC, const zd* zsite, zd* lu, int* nfloor,
+                hipStream_t s);
+void launch_ilu_solve(const int* list, int ni, const int* site, const SparsePattern& sp, const zd* lu, int trans,
+                      const zd* X, int64_t xs, int64_t ldx, zd* Y, int64_t ys, int64_t ldy, int w, zd* T, int64_t ts,
+                      hipStream_t s);

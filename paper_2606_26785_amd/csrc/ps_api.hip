@@ -26,13 +26,13 @@ void ps_default_params(ps_params* p)
     memset(p, 0, sizeof(*p));
     p->r = 8;
     p->k_max = 32;
-    p->rbar = 16;
+    p->rbar = 8;
     p->kbar_max = 64;
     p->max_iters = 300;
     p->precond = -1;
     p->tiles_x = 0;
     p->tiles_y = 0;
-    p->tile_points = 20;
+    p->tile_points = 80;
     p->tile_mem_gb = 48;
     p->batch = 20;
     p->recycle = 1;
@@ -53,6 +53,7 @@ void ps_default_params(ps_params* p)
     p->esc_iters = 30;
     p->cert_recycled = 0;
     p->lipschitz = 1;
+    p->reg_base = 0.02;
 }
 
 const char* ps_strerror(ps_status s)
@@ -96,9 +97,14 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
     if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0) || !(p.eta_abs >= 0) || p.eta_abs > 1e-8 ||
         !(p.tol_abs >= 0) || p.tol_abs > 1e-6 || p.esc_iters < 0)
         return fail(PS_EINVAL, "bad tolerances");
-    if (p.precond > 1 || p.precond < -1) return fail(PS_EINVAL, "precond must be -1, 0 or 1");
-    if (p.precond == 1 && d->kind != PS_DENSE)
-        return fail(PS_EUNSUPPORTED, "the base preconditioner needs a dense matrix in this version");
+    if (p.precond > 2 || p.precond < -1) return fail(PS_EINVAL, "precond must be -1, 0, 1 or 2");
+    if (p.precond >= 1 && d->kind != PS_DENSE && d->m != d->n)
+        return fail(PS_EUNSUPPORTED, "the sparse base preconditioner needs a square matrix");
+    const int pc = p.precond < 0 ? (d->kind == PS_DENSE ? 1 : (d->m == d->n ? 2 : 0)) : p.precond;
+    if (pc == 2 && p.rbar != p.r)
+        return fail(PS_EINVAL, "the two-level preconditioner runs its projection LOBPCG with block rbar = r");
+    if (!(p.eta_proj > 0) || !(p.tau_min > 0) || !(p.tau_max > 1.0) || !(p.reg_base >= 0) || p.reg_base > 1.0)
+        return fail(PS_EINVAL, "bad projection or rebuild thresholds");
     if (d->kind == PS_DENSE && !d->on_device) {
         for (int64_t j = 0; j < d->n; ++j)
             for (int64_t i = 0; i < 2 * d->m; ++i)
@@ -225,4 +231,75 @@ extern "C" ps_status ps_debug_precond(ps_matrix* h, double z_re, double z_im, do
     } catch (const std::exception& e) {
         return fail(PS_EDEVICE, e.what());
     }
+}
+
+// One refinement of the projection subspace at z against a regularised site
+// at z_dag, then Y = K_Ebar^{-1} W with the resulting two-level
+// preconditioner (eq. (twolevel)); Ebar (n x r) and Lambda_bar (r) out.
+extern "C" ps_status ps_debug_twolevel(ps_matrix* h, double zd_re, double zd_im, double z_re, double z_im,
+                                       const double* W, double* Y, double* Ebar, double* lam, int32_t* iters)
+{
+    if (!h || !W || !Y || !Ebar || !lam) return fail(PS_EINVAL, "NULL argument");
+    try {
+        Engine& E = h->eng;
+        if (!E.two_level) return fail(PS_EUNSUPPORTED, "no two-level preconditioner on this handle");
+        if (E.T < 1 || E.NS < 1) E.size_for(std::max(E.T, 1));
+        E.reset_slots();
+        std::vector<int> sl = E.build_regularized({zmake(zd_re, zd_im)});
+        if (sl.empty() || sl[0] < 0) return fail(PS_ENOMEM, "no preconditioner slot");
+        const int t = 0, r = E.r;
+        const int64_t n = E.n, sS = n * 3 * r;
+        E.tile_slot[t] = sl[0];
+        E.slot_ref[sl[0]]++;
+        E.usek[t] = 1;
+        E.phase[t] = 1;
+        E.use2l[t] = 0;
+        E.h_zt[t] = zmake(z_re, z_im);
+        std::vector<zd> hz(E.T, zmake(z_re, z_im));
+        E.h2d(E.d_z.p, hz.data(), sizeof(zd) * E.T);
+        std::vector<int> L = {t};
+        E.upload_list(L, E.d_list);
+        launch_randfill(E.d_list.p, 1, E.S.p, sS, n, n, r, nullptr, 0x7e57ull, E.st);
+        E.lob_start(L, 0x1234ull);
+        std::vector<int> done, okv;
+        int it = 0;
+        for (it = 0; it < 200 && done.empty(); ++it) E.lob_step(L, 0x9876ull + it, done, okv);
+        E.finv_apply(L, 0, E.S.p, sS, n, E.tE.p, n * r, n);
+        for (int j = 0; j < r; ++j) {
+            const double s = E.lob_sv[(size_t)t * r + j];
+            E.tlam_h[(size_t)t * r + j] = s * s;
+            lam[j] = s * s;
+        }
+        E.h2d(E.tLam.p, E.tlam_h.data(), sizeof(double) * E.T * r);
+        E.phase[t] = 0;
+        E.use2l[t] = 1;
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(E.Wres.p, W, sizeof(zd) * n * r, hipMemcpyHostToDevice));
+        E.precond_apply(L, E.Wres.p, n * r, E.S.p + (size_t)n * r, sS);
+        E.twolevel_add(L, E.Wres.p, n * r, E.S.p + (size_t)n * r, sS);
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(Y, E.S.p + (size_t)n * r, sizeof(zd) * n * r, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(Ebar, E.tE.p, sizeof(zd) * n * r, hipMemcpyDeviceToHost));
+        if (iters) *iters = it;
+        E.slot_ref[sl[0]]--;
+        E.tile_slot[t] = -1;
+        return PS_OK;
+    } catch (const std::exception& e) {
+        return fail(PS_EDEVICE, e.what());
+    }
+}
+
+// The regularisation shift d of the site last built by ps_debug_twolevel
+// (K = F^* F = N(z_dag) + d I) and gamma = ||F^{-1}||_2 (estimate).
+extern "C" ps_status ps_debug_site(ps_matrix* h, double* dreg, double* gamma)
+{
+    if (!h || !dreg || !gamma) return fail(PS_EINVAL, "NULL argument");
+    Engine& E = h->eng;
+    for (int s = 0; s < E.NS; ++s)
+        if (E.slot_valid[s]) {
+            *dreg = E.slot_dreg[s];
+            *gamma = E.slot_gam[s];
+            return PS_OK;
+        }
+    return fail(PS_EINVAL, "no site built");
 }

@@ -147,6 +147,32 @@ def test_triangular_full_grid_parity():
     assert res.stats["accepted"] > 0
 
 
+@pytest.mark.parametrize("grid", [12, 24])
+def test_two_level_preconditioner_parity(grid):
+    """The whole path with the two-level preconditioner of eq. (twolevel):
+    recycled projection subspaces per site (Alg. 4), projection refinement
+    and its update (Alg. 5), regularised base sites and the rebuild rule of
+    eq. (tauRecycle)."""
+    wl = workloads.triangular_disk(seed=1001, n=100, grid=grid)
+    zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
+    ref = _o1(wl.dense, zs)
+    res = _run(wl, precond=2)
+    _check_parity(wl, res, ref, _norm_dense(wl.dense), "two-level n=100 %dx%d" % (grid, grid))
+    assert res.stats["proj_refined"] > 0
+    assert (res.flags & P.FLAG_PROJ_REFINED).any()
+
+
+def test_two_level_toeplitz_parity():
+    wl = workloads.toeplitz_band(seed=1002, n=400, grid=16)
+    zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
+    band, kl, ku = oracle.band_from_dense(wl.dense)
+    ref = oracle.sigma_min_banded(band, wl.n, wl.n, kl, ku, zs)
+    nC = float(oracle.banded_smallest(band, wl.n, wl.n, kl, ku, 0.0, k=wl.n)[-1])
+    res = _run(wl, precond=2)
+    _check_parity(wl, res, ref, nC, "two-level toeplitz n=400 16x16")
+    assert res.stats["proj_refined"] > 0
+
+
 def test_toeplitz_reduced_parity():
     wl = workloads.toeplitz_band(seed=1002, n=400, grid=24)
     zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)

@@ -37,11 +37,18 @@ def test_create_shape_and_values():
 
 
 @pytest.mark.parametrize("field,value", [("r", 3), ("r", 18), ("k_max", 12), ("k_max", 128), ("rbar", 5),
-                                         ("kbar_max", 24), ("max_iters", 0), ("batch", 0), ("eta", 0.0),
-                                         ("eta_svd", -1.0), ("omega", 0.5), ("eta_abs", 2e-8),
-                                         ("tol_abs", -1.0), ("esc_iters", -1), ("precond", 2)])
+                                         ("kbar_max", 20), ("kbar_max", 72), ("max_iters", 0),
+                                         ("batch", 0), ("eta", 0.0), ("eta_svd", -1.0), ("omega", 0.5),
+                                         ("eta_abs", 2e-8), ("tol_abs", -1.0), ("esc_iters", -1), ("precond", 3),
+                                         ("eta_proj", 0.0), ("tau_max", 0.5), ("reg_base", -1.0),
+                                         ("tile_points", 0)])
 def test_create_rejects_bad_params(field, value):
     params = P.default_params(**{field: value})
+    assert _status(P.ps_create, dense=_dense(), params=params) == PS_EINVAL
+
+
+def test_two_level_block_sizes_must_match():
+    params = P.default_params(precond=2, rbar=4)
     assert _status(P.ps_create, dense=_dense(), params=params) == PS_EINVAL
 
 

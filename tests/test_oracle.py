@@ -307,3 +307,35 @@ def test_grid_points_inclusive_endpoints_and_order():
     assert oracle.grid_points(0.5, 9.0, -2.0, 7.0, 1, 1)[0] == complex(0.5, -2.0)
     one_row = oracle.grid_points(0.0, 1.0, 3.0, 4.0, 3, 1)
     assert list(one_row) == [3j, 0.5 + 3j, 1.0 + 3j]
+
+
+@pytest.mark.parametrize("N", [12, 20])
+def test_sparse_lu_oracle_matches_o1(N):
+    # O2 for square sparse C (banded LU + inverse subspace iteration) against
+    # the dense Jacobi oracle on reduced convection-diffusion instances
+    wl = workloads.convection_diffusion(N=N, grid=5)
+    zs = oracle.grid_points(*wl.region, 5, 5)
+    s2, steps = oracle.sigma_min_sparse_lu(wl.n, wl.n, wl.rowptr, wl.colind, wl.vals, zs)
+    s1, sw = oracle.sigma_min_dense(wl.to_dense(), zs)
+    nC = oracle.norm2_sparse(wl.n, wl.n, wl.rowptr, wl.colind, wl.vals)
+    assert (sw > 0).all() and (steps >= 0).all()
+    assert np.max(np.abs(s1 - s2)) <= 1e-12 * nC
+
+
+def test_sparse_lu_oracle_normal_closed_form():
+    # a sparse normal matrix: diagonal D (any bandwidth-0 C), sigma = min |d_i - z|
+    rng = np.random.default_rng(5)
+    n = 300
+    d = _cplx(rng, n) * 2.0
+    rowptr = np.arange(n + 1, dtype=np.int64)
+    colind = np.arange(n, dtype=np.int32)
+    zs = _cplx(rng, 12)
+    s, steps = oracle.sigma_min_sparse_lu(n, n, rowptr, colind, d, zs)
+    ref = np.min(np.abs(d[None, :] - zs[:, None]), axis=1)
+    assert np.max(np.abs(s - ref)) <= 1e-12 * np.max(np.abs(d))
+
+
+def test_norm2_sparse_matches_lapack():
+    wl = workloads.convection_diffusion(N=15, grid=3)
+    nC = oracle.norm2_sparse(wl.n, wl.n, wl.rowptr, wl.colind, wl.vals)
+    assert abs(nC - np.linalg.norm(wl.to_dense(), 2)) <= 1e-8 * nC
