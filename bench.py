@@ -237,8 +237,9 @@ def main():
         nxp = (wl.nx - 1) // k + 1
         nyp = (wl.ny - 1) // k + 1
         gp = P.ps_grid(re_lo, re_lo + (nxp - 1) * k * hx, im_lo, im_lo + (nyp - 1) * k * hy, nxp, nyp)
-        pp = P.default_params(recycle=0, verbose=0, tiles_x=args.tiles_x, tiles_y=args.tiles_y,
-                              batch=args.batch)
+        # no recycling: every point is its own tile, all in flight together
+        pp = P.default_params(recycle=0, verbose=0, tile_points=1, batch=args.batch,
+                              **({"k_max": 64, "tile_mem_gb": 96} if args.workload == "convdiff" else {}))
         matp = P.create_from_workload(wl, params=pp)
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
@@ -247,7 +248,7 @@ def main():
         tp = time.perf_counter() - tp0
         plain = {"value": nxp * nyp / tp, "unit": "pts/s", "points": nxp * nyp,
                  "sample": "every %d-th grid line in each direction of the same grid (%dx%d points, %.1f%% of "
-                           "the grid), no recycling, same tiles and batching" % (k, nxp, nyp,
+                           "the grid), no recycling, one point per tile, all points batched" % (k, nxp, nyp,
                                                                                  100.0 * nxp * nyp / npts),
                  "lobpcg_iters": resp.stats["lobpcg_iters"], "cert_tests": resp.stats["cert_tests"],
                  "rebuilds": resp.stats["rebuilds"], "uncertified": resp.stats["uncertified"]}

@@ -187,6 +187,8 @@ typedef struct {
     int64_t store_updates; /* updateRecy calls that appended a block (Alg. 2) */
     int64_t precond_iters; /* LOBPCG iterations that applied K^{-1} != I */
     int64_t repairs;       /* LOBPCG steps whose search space lost rank and was rebuilt */
+    int64_t mv_update;     /* operator column-applies made by updateRecy (3 r per
+                              singular update with S = [I_n; 0]: C Q, C^* C Q, C^* S Q) */
     double t_total_ms;     /* wall time of ps_eval */
     double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
     /* with profile >= 1: event-timed kernel classes (launches, device ms,

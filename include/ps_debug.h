@@ -39,6 +39,21 @@ ps_status ps_debug_twolevel(ps_matrix* h, double zd_re, double zd_im, double z_r
  * last ps_debug_twolevel call. */
 ps_status ps_debug_site(ps_matrix* h, double* dreg, double* gamma);
 
+/* The recycled singular store of `tile` as the last ps_eval left it (Sec.
+ * 2.2): its dimension k, the orthonormal basis V (n x k_max), W1 = C V
+ * (m x k_max), W3 = C^* C V and W4 = C^* S V (n x k_max), and the cached R
+ * factors R_A of [W1 W2] (2k_max square) and R_res of [W3 W4 W5 W6]
+ * (4k_max square); host column-major, the leading k columns valid.
+ * Errors: PS_EINVAL (tile out of range), PS_EDEVICE. */
+ps_status ps_debug_store(ps_matrix* h, int32_t tile, int32_t* k, double* V, double* W1, double* W3, double* W4,
+                         double* RA, double* Rres);
+
+/* The Ritz stage of recySing (Alg. 1 in its cached-R form) on that store at
+ * z: the k Ritz singular values xi (ascending), the residual norms
+ * ||T(z) V g_j - xi_j^2 V g_j|| of eq. (fastresidual) and the right vectors
+ * G (k_max x k, column-major).  Errors: PS_EINVAL (empty store). */
+ps_status ps_debug_ritz(ps_matrix* h, int32_t tile, double z_re, double z_im, double* xi, double* res, double* G);
+
 /* The ||C||_2 estimate used in the acceptance tests (power iteration). */
 double ps_debug_norm(const ps_matrix* h);
 

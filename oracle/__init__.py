@@ -204,10 +204,11 @@ def membership(sigma: np.ndarray, eps_levels) -> np.ndarray:
     return (np.asarray(sigma)[None, :] < eps).astype(np.uint8)
 
 
-def norm2_sparse(m: int, n: int, rowptr, colind, vals, rel: float = 1e-10, seed: int = 7) -> float:
+def norm2_sparse(m: int, n: int, rowptr, colind, vals, rel: float = 1e-9, seed: int = 7,
+                 max_iter: int = 3000) -> float:
     """||C||_2 of a CSR matrix by power iteration on C^* C, stopped when the
-    estimate changes by less than rel (relative).  It only scales
-    tolerances."""
+    estimate changes by less than rel (relative) or after max_iter steps (a
+    slightly low value only tightens the tolerances it scales)."""
     import scipy.sparse as sp
     A = sp.csr_matrix((np.asarray(vals, dtype=np.complex128), np.asarray(colind), np.asarray(rowptr)),
                       shape=(m, n))
@@ -215,7 +216,7 @@ def norm2_sparse(m: int, n: int, rowptr, colind, vals, rel: float = 1e-10, seed:
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     x /= np.linalg.norm(x)
     lam = 0.0
-    for _ in range(100000):
+    for _ in range(max_iter):
         y = A.conj().T @ (A @ x)
         new = float(np.linalg.norm(y))
         x = y / new

@@ -59,7 +59,7 @@ class ps_stats(ctypes.Structure):
         "points", "accepted", "refined", "uncertified", "lobpcg_iters", "proj_accepted",
         "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds", "certified", "lipschitz_redo",
         "guard_rejects", "cert_tests", "builds_shared", "builds_private", "ritz_jobs", "store_updates",
-        "precond_iters", "repairs")] + \
+        "precond_iters", "repairs", "mv_update")] + \
         [(n, ctypes.c_double) for n in ("t_total_ms", "t_ritz_ms", "t_lobpcg_ms", "t_update_ms",
                                         "t_precond_ms")] + \
         [("k_launches", ctypes.c_int64 * NCLASS), ("k_ms", ctypes.c_double * NCLASS),
@@ -110,6 +110,10 @@ def load():
     lib.ps_debug_twolevel.restype = ctypes.c_int
     lib.ps_debug_site.argtypes = [P, P, P]
     lib.ps_debug_site.restype = ctypes.c_int
+    lib.ps_debug_store.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P]
+    lib.ps_debug_store.restype = ctypes.c_int
+    lib.ps_debug_ritz.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P, P]
+    lib.ps_debug_ritz.restype = ctypes.c_int
     lib.ps_debug_norm.argtypes = [P]
     lib.ps_debug_norm.restype = ctypes.c_double
     _lib = lib
@@ -302,3 +306,29 @@ def debug_twolevel(mat: Matrix, zdag: complex, z: complex, W: np.ndarray):
     g = np.zeros(1)
     _check(lib.ps_debug_site(mat.handle, _ptr(d), _ptr(g)), "ps_debug_site")
     return Y, E, lam, int(it[0]), float(d[0]), float(g[0])
+
+
+def debug_store(mat: Matrix, tile: int, k_max: int):
+    """(k, V, W1, W3, W4, R_A, R_res) of a tile's recycled store (test hook)."""
+    m, n = mat.shape
+    K = k_max
+    V = np.empty((n, K), np.complex128, order="F")
+    W1 = np.empty((m, K), np.complex128, order="F")
+    W3 = np.empty((n, K), np.complex128, order="F")
+    W4 = np.empty((n, K), np.complex128, order="F")
+    RA = np.empty((2 * K, 2 * K), np.complex128, order="F")
+    Rr = np.empty((4 * K, 4 * K), np.complex128, order="F")
+    k = np.zeros(1, np.int32)
+    _check(load().ps_debug_store(mat.handle, int(tile), _ptr(k), _ptr(V), _ptr(W1), _ptr(W3), _ptr(W4), _ptr(RA),
+                                 _ptr(Rr)), "ps_debug_store")
+    return int(k[0]), V, W1, W3, W4, RA, Rr
+
+
+def debug_ritz(mat: Matrix, tile: int, z: complex, k: int, k_max: int):
+    """(xi, residual norms, G) of the Ritz stage on a tile's store (test hook)."""
+    xi = np.empty(k)
+    res = np.empty(k)
+    G = np.empty((k_max, k), np.complex128, order="F")
+    _check(load().ps_debug_ritz(mat.handle, int(tile), float(np.real(z)), float(np.imag(z)), _ptr(xi), _ptr(res),
+                                _ptr(G)), "ps_debug_ritz")
+    return xi, res, G[:k, :]

@@ -129,11 +129,13 @@ void Engine::update_store(const std::vector<int>& Lin)
     stats.store_updates += nt;
     // 3. operator blocks of the new basis block (before rotation)
     const int64_t sT1 = (int64_t)m * 3 * r;
+    const int64_t mv0 = stats.mv_M;
     launch_zero(Tn1.p, (int64_t)T * sT1, st);
     launch_copy_cols(d_list2.p, nt, Xw.p, sX, n, Tn1.p + (size_t)m * r, sT1, m, n, r, st);
     apply(false, d_list2.p, nt, Xw.p, sX, n, Tn1.p, sT1, m, r, nullptr);                 // C Q
     apply(true, d_list2.p, nt, Tn1.p, sT1, m, Tn2.p, sX, n, r, nullptr);                 // C^* C Q
     apply(true, d_list2.p, nt, Tn1.p + (size_t)m * r, sT1, m, Tn3.p, sX, n, r, nullptr); // C^* S Q
+    stats.mv_update += stats.mv_M - mv0;
     // 4. new k, then [kept | new] Qt for V and each W block
     for (int t : L) tiles[t].k = (qsel[t] + 1) * r;
     upload_k();

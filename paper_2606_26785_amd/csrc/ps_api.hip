@@ -303,3 +303,92 @@ extern "C" ps_status ps_debug_site(ps_matrix* h, double* dreg, double* gamma)
         }
     return fail(PS_EINVAL, "no site built");
 }
+
+// The recycled singular store of one tile as the last ps_eval left it.
+extern "C" ps_status ps_debug_store(ps_matrix* h, int32_t tile, int32_t* k, double* V, double* W1, double* W3,
+                                    double* W4, double* RA, double* Rres)
+{
+    if (!h || !k || !V || !W1 || !W3 || !W4 || !RA || !Rres) return fail(PS_EINVAL, "NULL argument");
+    try {
+        Engine& E = h->eng;
+        if (tile < 0 || tile >= E.T) return fail(PS_EINVAL, "tile out of range");
+        const int K = E.K;
+        const int64_t n = E.n, m = E.m;
+        *k = E.tiles.size() > (size_t)tile ? E.tiles[tile].k : 0;
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(V, E.sV.p + (size_t)tile * n * K, sizeof(zd) * n * K, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(W1, E.sW1.p + (size_t)tile * m * K, sizeof(zd) * m * K, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(W3, E.sW3.p + (size_t)tile * n * K, sizeof(zd) * n * K, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(W4, E.sW4.p + (size_t)tile * n * K, sizeof(zd) * n * K, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(RA, E.sRA.p + (size_t)tile * 4 * K * K, sizeof(zd) * 4 * K * K, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(Rres, E.sRres.p + (size_t)tile * 16 * K * K, sizeof(zd) * 16 * K * K,
+                         hipMemcpyDeviceToHost));
+        return PS_OK;
+    } catch (const std::exception& e) {
+        return fail(PS_EDEVICE, e.what());
+    }
+}
+
+// recySing (the Ritz stage) for one tile's store at z: all k Ritz values
+// (ascending), their residual norms ||T(z) V g_j - xi_j^2 V g_j|| and the
+// right vectors G (k x k, column-major, ld k_max).
+extern "C" ps_status ps_debug_ritz(ps_matrix* h, int32_t tile, double z_re, double z_im, double* xi, double* res,
+                                   double* G)
+{
+    if (!h || !xi || !res || !G) return fail(PS_EINVAL, "NULL argument");
+    try {
+        Engine& E = h->eng;
+        if (tile < 0 || tile >= E.T) return fail(PS_EINVAL, "tile out of range");
+        const int K = E.K;
+        const int k = E.tiles[tile].k;
+        if (k <= 0) return fail(PS_EINVAL, "empty store");
+        DBuf<int> jt;
+        DBuf<zd> jz, jg;
+        DBuf<double> jn, jx, jr;
+        DBuf<uint8_t> ja;
+        jt.alloc(1); jz.alloc(1); jg.alloc((size_t)K * K); jn.alloc(1); jx.alloc(K); jr.alloc(K); ja.alloc(1);
+        const zd z = zmake(z_re, z_im);
+        const double nrm = E.op.normC + sqrt(zabs2(z));
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(jt.p, &tile, sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(jz.p, &z, sizeof(zd), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(jn.p, &nrm, sizeof(double), hipMemcpyHostToDevice));
+        RitzArgs ra;
+        memset(&ra, 0, sizeof(ra));
+        ra.njobs = 1;
+        ra.job_tile = jt.p;
+        ra.kdim = E.d_k.p;
+        ra.z = jz.p;
+        ra.nrm = jn.p;
+        ra.RA = E.sRA.p;
+        ra.strideRA = (int64_t)4 * K * K;
+        ra.ldRA = 2 * K;
+        ra.Rres = E.sRres.p;
+        ra.strideRres = (int64_t)16 * K * K;
+        ra.ldRres = 4 * K;
+        ra.nres = 4;
+        ra.nv = k;
+        ra.ng = k;
+        ra.max_sweeps = 40;
+        ra.mode = 0;
+        ra.eta = E.P.eta;
+        ra.floor_c = 16.0;
+        ra.eta_abs = 0.0;
+        ra.normC = E.op.normC;
+        ra.xi = jx.p;
+        ra.res = jr.p;
+        ra.ldxi = K;
+        ra.Gout = jg.p;
+        ra.strideG = (int64_t)K * K;
+        ra.ldG = K;
+        ra.accept = ja.p;
+        launch_ritz(ra, K, E.st);
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(xi, jx.p, sizeof(double) * k, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(res, jr.p, sizeof(double) * k, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(G, jg.p, sizeof(zd) * K * k, hipMemcpyDeviceToHost));
+        return PS_OK;
+    } catch (const std::exception& e) {
+        return fail(PS_EDEVICE, e.what());
+    }
+}
