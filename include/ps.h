@@ -10,14 +10,23 @@
  * the epsilon-pseudospectrum, sigma_min < epsilon (strict), for a list of
  * epsilon levels.
  *
- * The method is the paper's Alg. 5 (psPrecRecy): Ritz singular pairs from a
- * recycled singular subspace (Sec. 2.2, Alg. 1), a residual acceptance test
- * (eq. (tolC)), and for rejected points a block LOBPCG-SVD (supplement,
- * Alg. SM1.1) preconditioned by the two-level preconditioner of eq.
- * (twolevel), whose projection subspace is recycled the same way (Sec. 3.2,
- * Alg. 4), with the adaptive subspace update of Alg. 2 and the
- * base-preconditioner rebuild rule of eq. (tauRecycle).  Every numerical
- * step runs in HIP kernels on the GPU in complex128.
+ * The method is the paper's Alg. 5 (psPrecRecy).  A point is first tried
+ * against the recycled singular subspace: Ritz singular pairs by the
+ * one-step Rayleigh-Ritz-SVD of Sec. 2.2 (Alg. 1, recySing), evaluated from
+ * cached R factors of the subspace's auxiliary blocks, and the residual test
+ * of eq. (tolC).  A rejected point runs a block LOBPCG-SVD (supplement,
+ * Alg. SM1.1) and its result enters the subspace by the adaptive update of
+ * Alg. 2.  The LOBPCG preconditioner is chosen by ps_params.precond:
+ *  - 1 (dense default): base preconditioner K = F^* F = N(z_dag) + delta I,
+ *    an exact Cholesky factor at sites z_dag placed by a base-only form of
+ *    the rebuild rule (eq. (tauRecycle) with the projection part empty);
+ *  - 2 (square CSR default): the two-level preconditioner of eq.
+ *    (twolevel): an incomplete-LU base (CSR) or a regularised Cholesky base
+ *    (dense), plus a projection subspace recycled by Alg. 4 (recyProj) and
+ *    eq. (tolTz), refined by LOBPCG-SVD on Mbar(z) = C(z) F^{-1} when the
+ *    test fails, and the full rebuild rule of eq. (tauRecycle);
+ *  - 0 (rectangular CSR default): K = I.
+ * Every numerical step runs in HIP kernels on the GPU in complex128.
  *
  * Conventions
  *  - Complex numbers are interleaved (re, im) doubles.  Dense matrices are
@@ -61,7 +70,7 @@ typedef enum {
 typedef enum { PS_DENSE = 0, PS_CSR = 1 } ps_kind;
 
 /* Number of event-timed kernel classes in ps_stats. */
-#define PS_NCLASS 8
+#define PS_NCLASS 9
 
 /* Input matrix C (m x n, m >= n >= 1). */
 typedef struct {
@@ -109,7 +118,15 @@ typedef struct {
     int32_t tile_points;/* auto partition: points per tile (default 80) */
     int32_t tile_mem_gb;/* auto partition: device memory for per-tile state
                            (default 48) */
+    int32_t site_mem_gb;/* device memory for preconditioner sites and their
+                           staging (dense: explicit inverse factors; sparse:
+                           incomplete-LU values and projection stores)
+                           (default 128) */
     int32_t batch;      /* b of the batch-zigzag traversal (default 20) */
+    int32_t traversal;  /* order of the points inside a tile: 0 batch zigzag
+                           (Sec. 2.3, default); 1 Hilbert curve; 2 Morton
+                           (Z) order -- the locality-preserving alternatives
+                           of Sec. 5.4 */
     int32_t recycle;    /* 1: recycled path; 0: plain per-point LOBPCG from a
                            seeded random start (the comparison solver) */
     double eta;         /* acceptance tolerance of eq. (tolC) (default 1e-6) */
@@ -195,13 +212,16 @@ typedef struct {
      * algorithmic flops and bytes per class).  Class 0: operator applies
      * C X, C^* Y (dense: matrix-core GEMM + split-K reduction; CSR: SpMM);
      * class 1: preconditioner applies K^{-1} W; class 2: Ritz extraction
-     * (per-point QR + Jacobi SVD + residual); class 3: matrix-core products
-     * inside factorizations (preconditioner sites, inertia tests); class 4:
-     * the diagonal-block steps of those factorizations and the forming of
-     * N(z).  With profile >= 2 also class 5: per-tile small dense kernels
-     * (Rayleigh-Ritz-SVD, Cholesky of Gram matrices, SVQB, rotations);
-     * class 6: tall-skinny Gram, product and norm kernels; class 7: the
-     * rest (copies, fills). */
+     * (per-point QR + Jacobi SVD + residual); class 3: the large
+     * matrix-core products inside factorizations (preconditioner sites,
+     * inertia tests: trailing updates and the F^{-1} block columns, on the
+     * 128 x 64-tile kernel); class 4: the diagonal-block steps of those
+     * factorizations and the forming of N(z); class 8: the narrow
+     * matrix-core products inside factorizations (row updates and diagonal
+     * F^{-1} blocks).  With profile >= 2 also class 5: per-tile small dense
+     * kernels (Rayleigh-Ritz-SVD, Cholesky of Gram matrices, SVQB,
+     * rotations); class 6: tall-skinny Gram, product and norm kernels;
+     * class 7: the rest (copies, fills). */
     int64_t k_launches[PS_NCLASS];
     double k_ms[PS_NCLASS];
     double k_flops[PS_NCLASS];
@@ -219,19 +239,27 @@ typedef struct {
 
 void ps_default_params(ps_params* p);
 
-/* Upload C, prepare the operators and the (empty) recycled stores.
+/* Upload C (Sec. 1: the m x n matrix whose pseudospectra are computed,
+ * m >= n, with C(z) = C - z I, eq. (defSquare)), prepare the operators
+ * (C and C^*; for dense C with a preconditioner also C^* C) and the empty
+ * recycled stores.  desc is read during the call only (unless on_device).
  * hip_stream: the hipStream_t all work is issued on (NULL = default).
  * Errors: PS_EINVAL (m < n, n < 1, bad CSR, NULL pointers, bad params),
- * PS_ENOMEM, PS_EDEVICE. */
+ * PS_EUNSUPPORTED (a preconditioner on a rectangular CSR matrix),
+ * PS_ENOMEM, PS_EDEVICE; *out is NULL on error. */
 ps_status ps_create(const ps_matrix_desc* desc, const ps_params* params, void* hip_stream,
                     ps_matrix** out);
 
-/* A grid over [re_lo, re_hi] x [im_lo, im_hi] with nx x ny points (ends
- * included).  Errors: PS_EINVAL (nx < 1, ny < 1, non-finite bounds). */
+/* The equispaced Cartesian grid of the experiments (Sec. 4) over
+ * [re_lo, re_hi] x [im_lo, im_hi] with nx x ny points (ends included), and
+ * its traversal plan: tiles of neighbouring points in batch-zigzag order
+ * (Sec. 2.3).  Errors: PS_EINVAL (nx < 1, ny < 1, non-finite bounds). */
 ps_status ps_grid(double re_lo, double re_hi, double im_lo, double im_hi, int32_t nx,
                   int32_t ny, ps_gridh** out);
 
-/* Evaluate sigma_min(C - z I) on every grid point.
+/* Evaluate sigma_min(C - z I) on every grid point (eq. (defSquareSVD):
+ * the smallest singular value, whose sublevel sets are the
+ * epsilon-pseudospectra of eq. (defSquare)), by Alg. 5.
  * sigma:  nx*ny doubles (host), sigma[j*nx+i].
  * member: n_eps*nx*ny bytes (host) or NULL; member[e*nx*ny + p] = sigma[p] < eps[e].
  * flags:  nx*ny bytes (host) or NULL; PS_FLAG_* bits.
@@ -247,6 +275,7 @@ const char* ps_strerror(ps_status s);
 
 /* Text of the last error raised on this thread (empty if none). */
 const char* ps_last_error(void);
+
 
 #ifdef __cplusplus
 }

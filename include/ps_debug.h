@@ -57,6 +57,14 @@ ps_status ps_debug_ritz(ps_matrix* h, int32_t tile, double z_re, double z_im, do
 /* The ||C||_2 estimate used in the acceptance tests (power iteration). */
 double ps_debug_norm(const ps_matrix* h);
 
+/* Host only (no device call): the traversal plan of an nx x ny grid cut
+ * into tx x ty tiles (Sec. 2.3 batch zigzag with band height b, or the
+ * Hilbert / Morton orders of Sec. 5.4 for traversal 1 / 2).  order receives
+ * the nx*ny point indices (j*nx + i) tile after tile, tile_start the
+ * tx*ty + 1 offsets of the tiles in it.  Errors: PS_EINVAL. */
+ps_status ps_debug_order(int32_t nx, int32_t ny, int32_t tx, int32_t ty, int32_t b, int32_t traversal,
+                         int32_t* order, int32_t* tile_start);
+
 #ifdef __cplusplus
 }
 #endif

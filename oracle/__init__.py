@@ -204,27 +204,20 @@ def membership(sigma: np.ndarray, eps_levels) -> np.ndarray:
     return (np.asarray(sigma)[None, :] < eps).astype(np.uint8)
 
 
-def norm2_sparse(m: int, n: int, rowptr, colind, vals, rel: float = 1e-9, seed: int = 7,
-                 max_iter: int = 3000) -> float:
-    """||C||_2 of a CSR matrix by power iteration on C^* C, stopped when the
-    estimate changes by less than rel (relative) or after max_iter steps (a
-    slightly low value only tightens the tolerances it scales)."""
+def norm2_sparse(m: int, n: int, rowptr, colind, vals, rel: float = 1e-12, seed: int = 7) -> float:
+    """||C||_2 = sigma_max(C) of a CSR matrix: the largest eigenvalue of the
+    Hermitian C^* C by ARPACK's implicitly restarted Lanczos (scipy eigsh,
+    relative tolerance rel, seeded start vector), square-rooted."""
     import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
     A = sp.csr_matrix((np.asarray(vals, dtype=np.complex128), np.asarray(colind), np.asarray(rowptr)),
                       shape=(m, n))
+    AH = A.conj().T.tocsr()
+    op = spla.LinearOperator((n, n), matvec=lambda x: AH @ (A @ x), dtype=np.complex128)
     rng = np.random.default_rng(seed)
-    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-    x /= np.linalg.norm(x)
-    lam = 0.0
-    for _ in range(max_iter):
-        y = A.conj().T @ (A @ x)
-        new = float(np.linalg.norm(y))
-        x = y / new
-        if abs(new - lam) <= rel * new:
-            lam = new
-            break
-        lam = new
-    return float(np.sqrt(lam))
+    v0 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    lam = spla.eigsh(op, k=1, which="LA", v0=v0, tol=rel, return_eigenvectors=False, ncv=min(n, 40))
+    return float(np.sqrt(lam[0]))
 
 
 def sigma_min_sparse_lu(m: int, n: int, rowptr, colind, vals, zs, block: int = 8, tol_rel: float = 1e-14,

@@ -30,7 +30,7 @@ FLAG_PROJ_REFINED = 8
 FLAG_REBUILD = 16
 FLAG_CERTIFIED = 32
 FLAG_LIPSCHITZ = 64
-NCLASS = 8          # PS_NCLASS: event-timed kernel classes in ps_stats
+NCLASS = 9          # PS_NCLASS: event-timed kernel classes in ps_stats
 
 
 class ps_matrix_desc(ctypes.Structure):
@@ -44,7 +44,8 @@ class ps_params(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("k_max", ctypes.c_int32), ("rbar", ctypes.c_int32),
                 ("kbar_max", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32), ("tile_points", ctypes.c_int32),
-                ("tile_mem_gb", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("tile_mem_gb", ctypes.c_int32), ("site_mem_gb", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("traversal", ctypes.c_int32),
                 ("recycle", ctypes.c_int32), ("eta", ctypes.c_double), ("eta_svd", ctypes.c_double),
                 ("eta_proj", ctypes.c_double), ("omega", ctypes.c_double), ("tau_min", ctypes.c_double),
                 ("tau_max", ctypes.c_double), ("zdag_re", ctypes.c_double), ("zdag_im", ctypes.c_double),
@@ -114,6 +115,8 @@ def load():
     lib.ps_debug_store.restype = ctypes.c_int
     lib.ps_debug_ritz.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P, P]
     lib.ps_debug_ritz.restype = ctypes.c_int
+    lib.ps_debug_order.argtypes = [ctypes.c_int32] * 6 + [P, P]
+    lib.ps_debug_order.restype = ctypes.c_int
     lib.ps_debug_norm.argtypes = [P]
     lib.ps_debug_norm.restype = ctypes.c_double
     _lib = lib
@@ -269,6 +272,14 @@ def debug_apply(mat: Matrix, X: np.ndarray, z: complex = 0j, herm: bool = False)
     _check(load().ps_debug_apply(mat.handle, int(herm), float(np.real(z)), float(np.imag(z)), _ptr(X), w,
                                  _ptr(Y)), "ps_debug_apply")
     return Y
+
+
+def debug_order(nx: int, ny: int, tx: int, ty: int, b: int, traversal: int):
+    """Traversal plan (host only): list of per-tile arrays of point indices."""
+    order = np.empty(nx * ny, dtype=np.int32)
+    start = np.empty(tx * ty + 1, dtype=np.int32)
+    _check(load().ps_debug_order(nx, ny, tx, ty, b, traversal, _ptr(order), _ptr(start)), "ps_debug_order")
+    return [order[start[t]:start[t + 1]] for t in range(tx * ty)]
 
 
 def create_from_workload(wl, params: ps_params | None = None, stream=None) -> Matrix:

@@ -96,6 +96,10 @@ struct Tile {
     bool done() const { return cursor >= order.size(); }
 };
 
+// grid partition into tx x ty tiles and the order of the points inside each
+// (traversal: 0 batch zigzag with band height b, 1 Hilbert, 2 Morton)
+void tile_orders(int nx, int ny, int tx, int ty, int b, int traversal, std::vector<Tile>& tiles);
+
 // HIP-event timing of kernel classes (enabled by ps_params.profile)
 struct KProf {
     std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -197,7 +201,8 @@ struct Engine {
     void precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, zd* Y, int64_t ys);
     void zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, const zd* A, int64_t lda, int64_t sA,
                int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
-               double beta, int upper = 0, int tri = 0, const int* gmap = nullptr, int cw = 0);
+               double beta, int upper = 0, int tri = 0, const int* gmap = nullptr, int cw = 0,
+               int64_t cols_total = -1);   // column-map mode: columns over all groups (for the flop count)
 
     // ---- two-level preconditioner (Sec. 3, eq. (twolevel), Alg. 4, Alg. 5)
     // Each preconditioner site (slot) carries a recycled projection subspace
@@ -259,6 +264,7 @@ struct Engine {
 
     KProf prof;
     int zgemm_cls = 1;        // profiling class of zgemm launches (3 inside factorizations)
+    bool use_wide = true;     // 128 x 64-tile kernel for large products
     ps_stats stats{};
     std::vector<Tile> tiles;
     std::vector<zd> zs;       // grid points of the current eval

@@ -82,7 +82,7 @@ __global__ void k_scale_cols_rsqrt(const int* list, zd* A, int64_t stride, int64
 // ---------------------------------------------------------------------------
 int KProf::begin(hipStream_t s, int c, double fl, double by)
 {
-    if (!on || (c >= 5 && level < 2)) return -1;
+    if (!on || (c >= 5 && c <= 7 && level < 2)) return -1;
     if (2 * used + 2 > ev.size()) {
         size_t old = ev.size();
         ev.resize(std::max<size_t>(64, 2 * old));
@@ -556,7 +556,8 @@ void Engine::size_for(int tiles)
     gram_ws_bytes = std::max<size_t>((size_t)256 << 20, t * (size_t)cmax * cmax * sizeof(zdd) * 2);
     gram_ws.alloc(gram_ws_bytes);
     const size_t maxw = (size_t)std::max(r, P.rbar);
-    const size_t kbw = (size_t)32 * std::max(P.kbar_max, 1);      // projection-store refresh: 32 sites x KB columns
+    // projection-store refresh: 32 sites x KB columns (two-level only)
+    const size_t kbw = (P.precond == 2) ? (size_t)32 * std::max(P.kbar_max, 1) : 0;
     if (op.kind == PS_DENSE)
         apply_ws.alloc((size_t)std::max(m, n) * std::max<size_t>(std::max<size_t>(t * maxw, 64), kbw) * 4);
     norm_ws.alloc(std::max<size_t>(1 << 20, t * 3 * r * 256));
@@ -572,8 +573,11 @@ void Engine::size_for(int tiles)
         // staging for up to 32 simultaneous constructions; the site pool holds
         // one slot per tile plus the staging count (so a free slot always
         // exists), within 128 GB
-        NBLD = 32;
-        const size_t cap = std::max<size_t>(2, ((size_t)128 << 30) / (nn * sizeof(zd)));
+        // sites and staging share site_mem_gb: NBLD staging pairs (N(z) and
+        // the factor) and NS slots of F^{-1}
+        const size_t tot = std::max<size_t>(4, ((size_t)P.site_mem_gb << 30) / (nn * sizeof(zd)));
+        NBLD = (int)std::min<size_t>(32, std::max<size_t>(1, tot / 6));
+        const size_t cap = std::max<size_t>(2, tot - 2 * (size_t)NBLD);
         NS = (int)std::min<size_t>(t + NBLD, cap);
         // with the two-level preconditioner a site serves a whole region
         if (two_level) NS = std::min(NS, 160);
@@ -586,7 +590,7 @@ void Engine::size_for(int tiles)
         // the projection stores (8 n x kbar blocks per site) bound the count
         NBLD = 8;
         const double per = 16.0 * ((double)op.spat.nnz + 4.0 * n + (two_level ? 9.0 : 1.0) * n * P.kbar_max);
-        NS = (int)std::max(2.0, std::min((double)t + NBLD, std::min(64.0, 24e9 / per)));
+        NS = (int)std::max(2.0, std::min((double)t + NBLD, std::min(64.0, P.site_mem_gb * 1e9 / 5.0 / per)));
         Slu.alloc((size_t)NS * op.spat.nnz);
         Svec.alloc((size_t)NS * 4 * n);
         pS.alloc((size_t)NS * n * std::max(P.kbar_max, 1));

@@ -167,7 +167,82 @@ void Engine::update_store(const std::vector<int>& Lin)
 // first rejected one; every scheduler step advances all running refinements
 // by one iteration, and a tile whose refinement ends updates its store and
 // becomes idle again.
-static void tile_orders(int nx, int ny, int tx, int ty, int b, std::vector<Tile>& tiles)
+// Hilbert curve on a 2^k x 2^k square: position d along the curve -> cell
+// (x, y), built level by level (each level places the quadrant from two
+// bits of d and reflects / transposes the coordinates so far, so that the
+// sub-curves join end to end)
+static void hilbert_cell(int side, int64_t d, int& x, int& y)
+{
+    x = y = 0;
+    for (int s = 1; s < side; s *= 2) {
+        const int qx = (int)(1 & (d / 2));
+        const int qy = (int)(1 & (d ^ qx));
+        if (qy == 0) {
+            if (qx == 1) {
+                x = s - 1 - x;
+                y = s - 1 - y;
+            }
+            std::swap(x, y);
+        }
+        x += s * qx;
+        y += s * qy;
+        d /= 4;
+    }
+}
+
+// interleaved bits of (x, y): the Morton (Z-order) key
+static uint64_t morton_key(uint32_t x, uint32_t y)
+{
+    uint64_t k = 0;
+    for (int bit = 0; bit < 32; ++bit) {
+        k |= (uint64_t)((x >> bit) & 1u) << (2 * bit);
+        k |= (uint64_t)((y >> bit) & 1u) << (2 * bit + 1);
+    }
+    return k;
+}
+
+// Points of the rectangle [x0, x1) x [y0, y1) in the chosen traversal:
+// 0 batch zigzag (bands of height b, columns visited in alternating
+// directions, a vertical snake inside each band), 1 Hilbert curve (the
+// curve on the enclosing power-of-two square, cells outside the rectangle
+// skipped), 2 Morton order.
+static void rect_order(int nx, int x0, int x1, int y0, int y1, int b, int traversal, std::vector<int64_t>& out)
+{
+    const int w = x1 - x0, h = y1 - y0;
+    if (traversal == 1) {
+        int side = 1;
+        while (side < std::max(w, h)) side *= 2;
+        for (int64_t d = 0; d < (int64_t)side * side; ++d) {
+            int x, y;
+            hilbert_cell(side, d, x, y);
+            if (x < w && y < h) out.push_back((int64_t)(y0 + y) * nx + (x0 + x));
+        }
+        return;
+    }
+    if (traversal == 2) {
+        std::vector<std::pair<uint64_t, int64_t>> pts;
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x) pts.push_back({morton_key((uint32_t)x, (uint32_t)y), (int64_t)(y0 + y) * nx + x0 + x});
+        std::sort(pts.begin(), pts.end());
+        for (auto& q : pts) out.push_back(q.second);
+        return;
+    }
+    int band = 0;
+    for (int yb = y0; yb < y1; yb += b, ++band) {
+        const int ye = std::min(y1, yb + b);
+        const bool ltr = (band % 2 == 0);
+        for (int ci = 0; ci < w; ++ci) {
+            const int x = ltr ? (x0 + ci) : (x1 - 1 - ci);
+            const bool up = (ci % 2 == 0);
+            for (int yi = 0; yi < ye - yb; ++yi) {
+                const int y = up ? (yb + yi) : (ye - 1 - yi);
+                out.push_back((int64_t)y * nx + x);
+            }
+        }
+    }
+}
+
+void tile_orders(int nx, int ny, int tx, int ty, int b, int traversal, std::vector<Tile>& tiles)
 {
     tiles.clear();
     for (int jy = 0; jy < ty; ++jy) {
@@ -175,19 +250,9 @@ static void tile_orders(int nx, int ny, int tx, int ty, int b, std::vector<Tile>
         for (int jx = 0; jx < tx; ++jx) {
             int x0 = (int)((int64_t)nx * jx / tx), x1 = (int)((int64_t)nx * (jx + 1) / tx);
             Tile t;
-            int band = 0;
-            for (int yb = y0; yb < y1; yb += b, ++band) {
-                int ye = std::min(y1, yb + b);
-                bool ltr = (band % 2 == 0);
-                for (int ci = 0; ci < x1 - x0; ++ci) {
-                    int x = ltr ? (x0 + ci) : (x1 - 1 - ci);
-                    bool up = (ci % 2 == 0);
-                    for (int yi = 0; yi < ye - yb; ++yi) {
-                        int y = up ? (yb + yi) : (ye - 1 - yi);
-                        t.order.push_back(y * nx + x);
-                    }
-                }
-            }
+            std::vector<int64_t> o;
+            rect_order(nx, x0, x1, y0, y1, b, traversal, o);
+            for (int64_t p : o) t.order.push_back((int)p);
             if (!t.order.empty()) tiles.push_back(std::move(t));
         }
     }
@@ -232,7 +297,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
     }
     ty = std::min(ty, ny);
     tx = std::min(tx, nx);
-    tile_orders(nx, ny, tx, ty, b, tiles);
+    tile_orders(nx, ny, tx, ty, b, P.traversal, tiles);
     size_for((int)tiles.size());
     for (auto& t : tiles) { t.cursor = 0; t.k = 0; }
     reset_slots();
@@ -741,12 +806,50 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
             if (!fsites.empty()) {
                 std::vector<char> pd;
                 std::vector<int> got = build_precond(fsites, &fmus, &pd, true);
+                // a tile whose shifted sites are all indefinite has an
+                // eigenvalue of N(z) far below xi^2 (xi is not yet
+                // sigma_min): it gets the site N(z) + delta I at z instead
+                // (kind 4: unlike kind 2 it leaves later shifts possible, for
+                // when xi has come down to the bottom of a cluster)
+                {
+                    std::vector<char> has_pd(T, 0), asked(T, 0);
+                    for (size_t i = 0; i < fsites.size(); ++i) {
+                        if (fkind[i] != 1 && fkind[i] != 3) continue;
+                        asked[fown[i]] = 1;
+                        if (got[i] >= 0 && pd[i]) has_pd[fown[i]] = 1;
+                    }
+                    std::vector<zd> xs;
+                    std::vector<double> xm;
+                    std::vector<int> xo;
+                    for (int t = 0; t < T; ++t)
+                        if (asked[t] && !has_pd[t] && !certified[t]) {
+                            xs.push_back(h_zt[t]);
+                            xm.push_back(0.0);
+                            xo.push_back(t);
+                        }
+                    if (!xs.empty()) {
+                        // the indefinite shifted sites are of no use: free
+                        // their slots first
+                        for (size_t i = 0; i < fsites.size(); ++i)
+                            if (got[i] >= 0 && !pd[i] && (fkind[i] == 1 || fkind[i] == 3)) {
+                                slot_valid[got[i]] = 0;
+                                got[i] = -1;
+                            }
+                        std::vector<char> pd2;
+                        std::vector<int> got2 = build_precond(xs, &xm, &pd2, true);
+                        for (size_t i = 0; i < xs.size(); ++i) {
+                            fsites.push_back(xs[i]); fmus.push_back(0.0); fown.push_back(xo[i]); fkind.push_back(4);
+                            got.push_back(got2[i]);
+                            pd.push_back(pd2[i]);
+                        }
+                    }
+                }
                 std::vector<int> pick(T, -1);
-                // preference: the closest shift (kind 1), then kind 3, then the exact site
-                auto rank = [](int kd) { return kd == 1 ? 0 : (kd == 3 ? 1 : 2); };
+                // preference: the closest shift (kind 1), then kind 3, then the exact sites
+                auto rank = [](int kd) { return kd == 1 ? 0 : (kd == 3 ? 1 : (kd == 2 ? 2 : 3)); };
                 for (size_t i = 0; i < fsites.size(); ++i) {
                     const int t = fown[i];
-                    const bool usable = got[i] >= 0 && (fkind[i] == 2 || pd[i]) && !certified[t];
+                    const bool usable = got[i] >= 0 && (fkind[i] == 2 || fkind[i] == 4 || pd[i]) && !certified[t];
                     if (usable && (pick[t] < 0 || rank(fkind[i]) < rank(fkind[pick[t]]))) pick[t] = (int)i;
                 }
                 for (size_t i = 0; i < fsites.size(); ++i) {
@@ -757,7 +860,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                         tile_slot[t] = sl;
                         slot_ref[sl]++;
                         usek[t] = 1;
-                        if (fkind[i] != 3) site_exact[t] = 1;
+                        if (fkind[i] == 1 || fkind[i] == 2) site_exact[t] = 1;
                         use2l[t] = 0;   // the projection vectors belong to the previous site
                     } else {
                         slot_valid[sl] = 0;
@@ -816,12 +919,16 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                         tlam_h[(size_t)t * r + j] = l;
                         if (l <= P.tau_min) rb = j + 1;
                     }
+                    // with no pencil eigenvalue below tau_min the paper's
+                    // r_breve is 0 and nothing would be stored, so every later
+                    // point would repeat this refinement; the block is then
+                    // stored with all its columns in the omega test
                     const int sl = tile_slot[t];
-                    if (rb > 0 && !seen[sl]) {
+                    if (!seen[sl]) {
                         seen[sl] = 1;
                         us.push_back(sl);
                         ut.push_back(t);
-                        ub.push_back(rb);
+                        ub.push_back(rb > 0 ? rb : r);
                     }
                     if (tlam_h[(size_t)t * r + r - 1] < P.tau_min && !site_at(t)) rebuild.push_back(t);
                     else go.push_back(t);

@@ -8,7 +8,7 @@
 
 void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, const zd* A, int64_t lda, int64_t sA,
                    int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
-                   double beta, int upper, int tri, const int* gmap, int cw)
+                   double beta, int upper, int tri, const int* gmap, int cw, int64_t cols_total)
 {
     if (nt <= 0 || M <= 0 || N <= 0) return;
     ZgemmArgs a;
@@ -49,11 +49,22 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
         a.splitk = sk;
         a.ws = zgemm_ws.p;
     }
-    double fl = 8.0 * (double)M * N * Kd * nt * ((upper || tri) ? 0.5 : 1.0);
-    double by = 16.0 * nt * ((double)M * Kd * (tri ? 0.5 : 1.0) + (double)Kd * N +
-                             (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
-    int pi = prof.begin(st, zgemm_cls, fl, by);
-    launch_zgemm(a, nt, st, zgemm_cls == 3 ? 1 : 0);
+    // algorithmic work: in column-map mode N is the widest group, the
+    // columns actually multiplied are cols_total over all groups
+    const double ncols = (gmap && cols_total >= 0) ? (double)cols_total : (double)N * nt;
+    double fl = 8.0 * (double)M * ncols * Kd * ((upper || tri) ? 0.5 : 1.0);
+    double by = 16.0 * ((double)nt * M * Kd * (tri ? 0.5 : 1.0) + (double)Kd * ncols +
+                        (double)M * ncols * (beta != 0.0 ? 2.0 : 1.0));
+    const bool wide = use_wide && !gmap && M >= 128 && N >= 64 && Kd >= 32;
+    // inside factorizations: class 3 for the wide kernel, 8 for the narrow one
+    int pi = prof.begin(st, (zgemm_cls == 3 && !wide) ? 8 : zgemm_cls, fl, by);
+    if (wide) {
+        // large products: wide tiles fill the chip without splitting K
+        a.splitk = 1;
+        launch_zgemm_wide(a, nt, st);
+    } else {
+        launch_zgemm(a, nt, st, zgemm_cls == 3 ? 1 : 0);
+    }
     prof.end(st, pi);
 }
 
@@ -126,10 +137,10 @@ void Engine::precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, z
     const int* gm = d_gmap.p + ng;
     // T = F^{-*} W (F^{-*} lower triangular: A = Finv read conjugate-transposed)
     zgemm(d_gmap.p, ng, n, (int64_t)maxc * r, n, Finv.p, n, nn, 1, W, n, ws, Tn2.p, n, (int64_t)n * r, 1.0, 0.0, 0,
-          2, gm, r);
+          2, gm, r, (int64_t)nt * r);
     // Y = F^{-1} T
     zgemm(d_gmap.p, ng, n, (int64_t)maxc * r, n, Finv.p, n, nn, 0, Tn2.p, n, (int64_t)n * r, Y, n, ys, 1.0, 0.0, 0,
-          1, gm, r);
+          1, gm, r, (int64_t)nt * r);
 }
 
 // Build one site per entry of `sites` (z_dag): N(z_dag) + delta I, its upper

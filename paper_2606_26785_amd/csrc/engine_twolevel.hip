@@ -202,7 +202,7 @@ void Engine::finv_apply(const std::vector<int>& L, int trans, const zd* X, int64
     const int64_t nn = n * n;
     // Finv is upper triangular; F^{-*} is read as its conjugate transpose (lower)
     zgemm(d_gmap.p, ng, n, (int64_t)maxc * r, n, Finv.p, n, nn, trans ? 1 : 0, X, ldx, xs, Y, ldy, ys, 1.0, 0.0, 0,
-          trans ? 2 : 1, d_gmap.p + ng, r);
+          trans ? 2 : 1, d_gmap.p + ng, r, (int64_t)nt * r);
 }
 
 void Engine::op_apply(bool herm, const std::vector<int>& L, const zd* X, int64_t xs, int64_t ldx, zd* Y, int64_t ys,

@@ -149,29 +149,56 @@ void launch_dense_apply(DenseApplyArgs& a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
+// CSR SpMM: one thread per (row, group of CSR_CW right-hand-side columns),
+// the columns of all listed tiles flattened (tile-major, w per tile).  The
+// row's values and column indices are loaded once per group and used for
+// every column of it; neighbouring threads take neighbouring rows, so the
+// loads of X (same stencil offset) and the stores of Y are coalesced.
+#define CSR_CW 8
 __global__ void __launch_bounds__(NT) k_csr_apply(CsrApplyArgs a)
 {
     const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (row >= a.m) return;
-    const int tile = a.list[blockIdx.y];
+    const int q0 = blockIdx.y * CSR_CW;
+    const int qtot = a.ntiles * a.w;
+    const int nq = min(CSR_CW, qtot - q0);
+    const zd* xc[CSR_CW];
+    zd* yc[CSR_CW];
+    zd zz[CSR_CW];
+    zd acc[CSR_CW];
+#pragma unroll
+    for (int k = 0; k < CSR_CW; ++k) {
+        const int q = q0 + (k < nq ? k : 0);
+        const int tile = a.list[q / a.w], j = q % a.w;
+        xc[k] = a.X + (size_t)tile * a.xstride + (size_t)j * a.ldx;
+        yc[k] = a.Y + (size_t)tile * a.ystride + (size_t)j * a.ldy;
+        zz[k] = zmake(0.0, 0.0);
+        if (a.z) { zz[k] = a.z[tile]; if (a.conjz) zz[k].y = -zz[k].y; }
+        acc[k] = zmake(0.0, 0.0);
+    }
     const int64_t b = a.rowptr[row], e = a.rowptr[row + 1];
-    const zd* X = a.X + (size_t)tile * a.xstride;
-    zd* Y = a.Y + (size_t)tile * a.ystride;
-    zd zz = zmake(0.0, 0.0);
-    if (a.z) { zz = a.z[tile]; if (a.conjz) zz.y = -zz.y; }
-    for (int j = 0; j < a.w; ++j) {
-        const zd* xc = X + (size_t)j * a.ldx;
-        zd s = zmake(0.0, 0.0);
-        for (int64_t p = b; p < e; ++p) zfma(s, a.vals[p], xc[a.colind[p]]);
-        if (a.z && row < a.nshift) s = zsub(s, zmul(zz, xc[row]));
-        Y[row + (size_t)j * a.ldy] = s;
+    for (int64_t p = b; p < e; ++p) {
+        const zd v = a.vals[p];
+        const int32_t c = a.colind[p];
+#pragma unroll
+        for (int k = 0; k < CSR_CW; ++k)
+            if (k < nq) zfma(acc[k], v, xc[k][c]);
+    }
+#pragma unroll
+    for (int k = 0; k < CSR_CW; ++k) {
+        if (k < nq) {
+            zd s = acc[k];
+            if (a.z && row < a.nshift) s = zsub(s, zmul(zz[k], xc[k][row]));
+            yc[k][row] = s;
+        }
     }
 }
 
 void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s)
 {
-    if (a.ntiles <= 0) return;
-    dim3 g((unsigned)((a.m + NT - 1) / NT), a.ntiles);
+    if (a.ntiles <= 0 || a.w <= 0) return;
+    const int qtot = a.ntiles * a.w;
+    dim3 g((unsigned)((a.m + NT - 1) / NT), (unsigned)((qtot + CSR_CW - 1) / CSR_CW));
     hipLaunchKernelGGL(k_csr_apply, g, dim3(NT), 0, s, a);
 }
 
@@ -340,4 +367,132 @@ void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact)
         dim3 g2((unsigned)((a.M * a.N + NT - 1) / NT), nbatch);
         hipLaunchKernelGGL(k_zgemm_reduce, g2, dim3(NT), 0, s, a, nbatch);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Wide-tile batched complex GEMM for the factorisations (trailing Hermitian
+// updates and the large products that form F^{-1}):
+//   C_b = alpha op(A_b) B_b + beta C_b, op(A) = A or A^*,
+// 128 x 64 output tiles per workgroup, each of the four waves owning a
+// 64 x 32 quadrant (4 x 2 blocks of 16 x 16, re/im accumulators), K staged
+// 16 at a time through LDS with the next K tile loaded into registers while
+// the matrix cores work.  Per 4-deep K step a wave reads 6 complex operand
+// fragments from LDS for 32 v_mfma_f64_16x16x4f64 (the 64 x 32 kernel above:
+// 3 for 8), and a K tile of 128 + 64 rows carries 16 x 128 x 64 complex
+// multiply-adds (twice the flop per byte of the 64 x 32 tile).  upper: only
+// tiles touching the upper triangle of C; tri: A upper (1) or lower (2)
+// triangular, zero K ranges skipped.
+#define WBM 128
+#define WBN 64
+#define WBK 16
+__global__ void __launch_bounds__(NT) k_zgemm_wide(ZgemmArgs a)
+{
+    __shared__ zd As[WBK][WBM + 1];
+    __shared__ zd Bs[WBK][WBN + 1];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int64_t i0 = (int64_t)blockIdx.x * WBM;
+    const int64_t j0 = (int64_t)blockIdx.y * WBN;
+    const int tile = a.list ? a.list[blockIdx.z] : blockIdx.z;
+    if (a.upper && i0 > j0 + WBN - 1) return;
+    if (j0 >= a.N) return;
+    int64_t kbeg = 0, kend = a.K;
+    if (a.tri == 1 && kbeg < i0) kbeg = (i0 / WBK) * WBK;
+    if (a.tri == 2 && kend > i0 + WBM) kend = i0 + WBM;
+    const zd* A = a.A + (size_t)tile * a.strideA;
+    const zd* B = a.B + (size_t)tile * a.strideB;
+    zd* C = a.C + (size_t)tile * a.strideC;
+    dvec4 acc_re[8], acc_im[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        acc_re[q] = (dvec4){0.0, 0.0, 0.0, 0.0};
+        acc_im[q] = (dvec4){0.0, 0.0, 0.0, 0.0};
+    }
+    const int mrow = lane & 15, kq = lane >> 4;
+    constexpr int AQ = WBM * WBK / NT, BQ = WBN * WBK / NT;   // 8, 4
+    zd ra[AQ], rb[BQ];
+    auto gload = [&](int64_t kt) {
+        if (a.opA == 0) {
+            const int64_t gi = i0 + tid % WBM;
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) {
+                const int64_t gk = kt + tid / WBM + (NT / WBM) * q;
+                ra[q] = (gi < a.M && gk < kend) ? A[gi + gk * a.lda] : zmake(0.0, 0.0);
+            }
+        } else {
+            const int64_t gk = kt + tid % WBK;
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) {
+                const int64_t gi = i0 + tid / WBK + (NT / WBK) * q;
+                ra[q] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
+            }
+        }
+        const int64_t gk = kt + tid % WBK;
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int64_t gj = j0 + tid / WBK + (NT / WBK) * q;
+            rb[q] = (gj < a.N && gk < kend) ? B[gk + gj * a.ldb] : zmake(0.0, 0.0);
+        }
+    };
+    if (kbeg < kend) gload(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += WBK) {
+        if (a.opA == 0) {
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) As[tid / WBM + (NT / WBM) * q][tid % WBM] = ra[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < AQ; ++q) As[tid % WBK][tid / WBK + (NT / WBK) * q] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) Bs[tid % WBK][tid / WBK + (NT / WBK) * q] = rb[q];
+        __syncthreads();
+        if (k0 + WBK < kend) gload(k0 + WBK);
+#pragma unroll
+        for (int ks = 0; ks < WBK; ks += 4) {
+            zd av[4], bv[2];
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) av[r4] = As[ks + kq][wr * 64 + r4 * 16 + mrow];
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) bv[c2] = Bs[ks + kq][wc * 32 + c2 * 16 + mrow];
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const double ar = av[r4].x, ai = av[r4].y, nai = -av[r4].y;
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    const int q = r4 * 2 + c2;
+                    acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv[c2].x, acc_re[q], 0, 0, 0);
+                    acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bv[c2].y, acc_re[q], 0, 0, 0);
+                    acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv[c2].y, acc_im[q], 0, 0, 0);
+                    acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bv[c2].x, acc_im[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // D layout: lane l, element v -> row (l / 16) + 4 v, column l % 16 of a 16 x 16 block
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4)
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int q = r4 * 2 + c2;
+            const int64_t col = j0 + wc * 32 + c2 * 16 + (lane & 15);
+            if (col >= a.N) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = i0 + wr * 64 + r4 * 16 + (lane >> 4) + 4 * v;
+                if (row >= a.M) continue;
+                zd val = zmake(a.alpha * acc_re[q][v], a.alpha * acc_im[q][v]);
+                zd* cp = C + row + col * a.ldc;
+                if (a.beta != 0.0) val = zadd(val, *cp);
+                *cp = val;
+            }
+        }
+}
+
+void launch_zgemm_wide(const ZgemmArgs& a, int nbatch, hipStream_t s)
+{
+    if (nbatch <= 0 || a.M <= 0 || a.N <= 0) return;
+    dim3 g((unsigned)((a.M + WBM - 1) / WBM), (unsigned)((a.N + WBN - 1) / WBN), nbatch);
+    hipLaunchKernelGGL(k_zgemm_wide, g, dim3(NT), 0, s, a);
 }

@@ -11,6 +11,8 @@
 //  * k_svqb      orthonormalising transform of a block (SVQB).
 //  * k_rotations block unitary rotations restoring the QL form of the
 //                recycled basis (Sec. 2.2.2, eq. (blkGS)).
+#include <mutex>
+
 #include "zdev.h"
 #include "kernels.h"
 
@@ -617,16 +619,20 @@ int small_kernels_max_lds() { return g_max_lds; }
 void small_kernels_init()
 {
     // Ask for the device's full LDS per workgroup for the LDS-resident
-    // kernels; if the runtime refuses, keep the default limit and clear the
+    // kernels, once per process (handles may be created from several
+    // threads); if the runtime refuses, keep the default limit and clear the
     // error so that it does not surface at a later call.
-    int dev = 0, mx = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && mx > 0)
-        g_max_lds = mx;
-    const void* ks[] = {(const void*)k_ritz, (const void*)k_rr_hl, (const void*)k_svqb, (const void*)k_rotations};
-    for (const void* k : ks) {
-        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, g_max_lds - 4096) != hipSuccess)
-            (void)hipGetLastError();
-    }
-    (void)hipGetLastError();
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, mx = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && mx > 0)
+            g_max_lds = mx;
+        const void* ks[] = {(const void*)k_ritz, (const void*)k_rr_hl, (const void*)k_svqb, (const void*)k_rotations};
+        for (const void* k : ks) {
+            if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, g_max_lds - 4096) != hipSuccess)
+                (void)hipGetLastError();
+        }
+        (void)hipGetLastError();
+    });
 }

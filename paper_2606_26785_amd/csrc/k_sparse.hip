@@ -91,32 +91,44 @@ struct SpSolveArgs {
     int conj;               // 1: conjugate the values
     int64_t r0, r1;         // rows of this colour
 };
+// one thread per (row of the colour, group of up to TRSV_CW columns): the
+// row's entries are loaded once and used for every column of the group
+#define TRSV_CW 8
 __global__ void k_sptrsv_color(SpSolveArgs a)
 {
     const int item = a.list[blockIdx.y];
     const int s = a.site ? a.site[item] : item;
     const int64_t cnt = a.r1 - a.r0;
-    const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (g >= cnt * a.w) return;
-    const int64_t i = a.r0 + g % cnt;
-    const int c = (int)(g / cnt);
+    const int64_t nrb = (cnt + NT - 1) / NT;
+    const int64_t rb = blockIdx.x % nrb;
+    const int c0 = (int)(blockIdx.x / nrb) * TRSV_CW;
+    const int64_t g = rb * NT + threadIdx.x;
+    if (g >= cnt) return;
+    const int nc = min(TRSV_CW, a.w - c0);
+    const int64_t i = a.r0 + g;
     const zd* v = a.lu + (size_t)s * a.nnz;
-    zd* x = a.X + (size_t)item * a.xs + (size_t)c * a.ldx;
-    zd acc = x[i];
+    zd* x = a.X + (size_t)item * a.xs + (size_t)c0 * a.ldx;
+    zd acc[TRSV_CW];
+#pragma unroll
+    for (int k = 0; k < TRSV_CW; ++k) acc[k] = (k < nc) ? x[i + (size_t)k * a.ldx] : zmake(0.0, 0.0);
     for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
         const int32_t j = a.ci[p];
         if (a.part == 0 ? j >= i : j <= i) continue;
         zd val = v[a.map ? a.map[p] : p];
         if (a.conj) val = zconj(val);
-        acc = zsub(acc, zmul(val, x[j]));
+#pragma unroll
+        for (int k = 0; k < TRSV_CW; ++k)
+            if (k < nc) acc[k] = zsub(acc[k], zmul(val, x[j + (size_t)k * a.ldx]));
     }
+    zd dinv = zmake(1.0, 0.0);
     if (!a.unit) {
         zd d = v[a.diag[i]];
         if (a.conj) d = zconj(d);
-        const double d2 = zabs2(d);
-        acc = zscale(zcmul(d, acc), 1.0 / d2);
+        dinv = zscale(zconj(d), 1.0 / zabs2(d));
     }
-    x[i] = acc;
+#pragma unroll
+    for (int k = 0; k < TRSV_CW; ++k)
+        if (k < nc) x[i + (size_t)k * a.ldx] = a.unit ? acc[k] : zmul(dinv, acc[k]);
 }
 
 // Y[:, c] = X[perm, c] (gather, mode 0) or Y[perm, c] = X[:, c] (scatter, mode 1)
@@ -176,7 +188,8 @@ static void solve_pass(const int* list, int ni, const int* site, const SparsePat
         a.r0 = sp.cptr[c];
         a.r1 = sp.cptr[c + 1];
         if (a.r1 <= a.r0) continue;
-        dim3 g((unsigned)(((a.r1 - a.r0) * w + NT - 1) / NT), ni);
+        const int64_t nrb = (a.r1 - a.r0 + NT - 1) / NT;
+        dim3 g((unsigned)(nrb * ((w + TRSV_CW - 1) / TRSV_CW)), ni);
         hipLaunchKernelGGL(k_sptrsv_color, g, dim3(NT), 0, s, a);
     }
 }

@@ -191,6 +191,8 @@ struct ZgemmArgs {
     const int* gtile; const int* goff; const int* gcnt; int cw;
 };
 void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact = 0);
+// 128 x 64 tiles, no column map, no split K (large factorisation products)
+void launch_zgemm_wide(const ZgemmArgs& a, int nbatch, hipStream_t s);
 
 // dense base preconditioner (k_precond.hip)
 #define PRE_NB 32

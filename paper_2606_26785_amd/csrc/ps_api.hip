@@ -34,7 +34,9 @@ void ps_default_params(ps_params* p)
     p->tiles_y = 0;
     p->tile_points = 80;
     p->tile_mem_gb = 48;
+    p->site_mem_gb = 128;
     p->batch = 20;
+    p->traversal = 0;
     p->recycle = 1;
     p->eta = 1e-6;
     p->eta_svd = 1e-9;
@@ -93,7 +95,9 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
     if (p.kbar_max < p.rbar || p.kbar_max % p.rbar || p.kbar_max > 64)
         return fail(PS_EINVAL, "kbar_max must be a multiple of rbar, <= 64");
     if (p.max_iters < 1 || p.batch < 1) return fail(PS_EINVAL, "max_iters and batch must be positive");
-    if (p.tile_points < 1 || p.tile_mem_gb < 1) return fail(PS_EINVAL, "tile_points and tile_mem_gb must be positive");
+    if (p.traversal < 0 || p.traversal > 2) return fail(PS_EINVAL, "traversal must be 0, 1 or 2");
+    if (p.tile_points < 1 || p.tile_mem_gb < 1 || p.site_mem_gb < 1)
+        return fail(PS_EINVAL, "tile_points, tile_mem_gb and site_mem_gb must be positive");
     if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0) || !(p.eta_abs >= 0) || p.eta_abs > 1e-8 ||
         !(p.tol_abs >= 0) || p.tol_abs > 1e-6 || p.esc_iters < 0)
         return fail(PS_EINVAL, "bad tolerances");
@@ -207,6 +211,23 @@ extern "C" ps_status ps_debug_apply(ps_matrix* h, int32_t herm, double z_re, dou
     } catch (const std::exception& e) {
         return fail(PS_EDEVICE, e.what());
     }
+}
+
+extern "C" ps_status ps_debug_order(int32_t nx, int32_t ny, int32_t tx, int32_t ty, int32_t b, int32_t traversal,
+                                    int32_t* order, int32_t* tile_start)
+{
+    if (!order || !tile_start) return fail(PS_EINVAL, "NULL argument");
+    if (nx < 1 || ny < 1 || tx < 1 || ty < 1 || tx > nx || ty > ny || b < 1 || traversal < 0 || traversal > 2)
+        return fail(PS_EINVAL, "bad grid, tiling or traversal");
+    std::vector<Tile> tiles;
+    tile_orders(nx, ny, tx, ty, b, traversal, tiles);
+    int64_t pos = 0;
+    for (size_t t = 0; t < tiles.size(); ++t) {
+        tile_start[t] = (int32_t)pos;
+        for (int p : tiles[t].order) order[pos++] = p;
+    }
+    tile_start[tiles.size()] = (int32_t)pos;
+    return PS_OK;
 }
 
 extern "C" double ps_debug_norm(const ps_matrix* h) { return h ? h->eng.op.normC : 0.0; }

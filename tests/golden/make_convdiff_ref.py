@@ -56,7 +56,9 @@ def main():
             sig += d["sigma"]
             steps += d["steps"]
         order = np.argsort(idx)
-        out = {k: meta[k] for k in ("workload", "N", "n", "nx", "ny", "region", "normC", "oracle")}
+        out = {k: meta[k] for k in ("workload", "N", "n", "nx", "ny", "region", "oracle")}
+        wl = workloads.convection_diffusion()
+        out["normC"] = oracle.norm2_sparse(wl.m, wl.n, wl.rowptr, wl.colind, wl.vals)
         out["indices"] = [int(idx[i]) for i in order]
         out["sigma"] = [float(sig[i]) for i in order]
         out["steps"] = [int(steps[i]) for i in order]

@@ -147,6 +147,17 @@ def test_triangular_full_grid_parity():
     assert res.stats["accepted"] > 0
 
 
+@pytest.mark.parametrize("traversal", [1, 2])
+def test_traversal_parity(traversal):
+    """The Hilbert (1) and Morton (2) orders of Sec. 5.4 inside each tile
+    instead of batch zigzag: same bar, same oracle."""
+    wl = workloads.triangular_disk(seed=1001, n=100, grid=24)
+    zs = oracle.grid_points(*wl.region, wl.nx, wl.ny)
+    ref = _o1(wl.dense, zs)
+    res = _run(wl, traversal=traversal, tile_points=144)
+    _check_parity(wl, res, ref, _norm_dense(wl.dense), "triangular n=100 24x24 traversal %d" % traversal)
+
+
 @pytest.mark.parametrize("grid", [12, 24])
 def test_two_level_preconditioner_parity(grid):
     """The whole path with the two-level preconditioner of eq. (twolevel):

@@ -263,3 +263,26 @@ WORKLOADS = {
     "dense-toeplitz-n4000": lambda: toeplitz_band(),
     "csr-convdiff-n250000": lambda: convection_diffusion(),
 }
+
+
+def serving_requests(seed: int = 1005, n_req: int = 512, dense_range=(256, 4096), sparse_N_range=(100, 447),
+                     grid_range=(32, 128), eps=EPS_6) -> List[Workload]:
+    """A stream of pseudospectrum requests: each one dense (as
+    ``triangular_disk``, n ~ U{dense_range}, region [-2,2]^2) with probability
+    1/2, else sparse (as ``convection_diffusion``, N ~ U{sparse_N_range}, n =
+    N^2, region near its spectral boundary); grid side s ~ U{grid_range}.
+    Per request i the draws, in order, are: kind (u < 1/2 is dense), size,
+    grid side; request i's matrix then uses seed 10 * seed + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_req):
+        dense = rng.random() < 0.5
+        size = int(rng.integers(dense_range[0], dense_range[1] + 1)) if dense else \
+            int(rng.integers(sparse_N_range[0], sparse_N_range[1] + 1))
+        s = int(rng.integers(grid_range[0], grid_range[1] + 1))
+        if dense:
+            out.append(triangular_disk(seed=10 * seed + i, n=size, grid=s, eps=eps, name="req-%d-dense" % i))
+        else:
+            out.append(convection_diffusion(seed=10 * seed + i, N=size, grid=s, eps=eps,
+                                            name="req-%d-convdiff" % i))
+    return out
