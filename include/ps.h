@@ -276,6 +276,24 @@ const char* ps_strerror(ps_status s);
 /* Text of the last error raised on this thread (empty if none). */
 const char* ps_last_error(void);
 
+/* Operator apply without allocation, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same operation as
+ * ps_debug_apply: Y = C(z) X (herm = 0; X n x w, Y m x w) or
+ * Y = C(z)^* X (herm = 1; X m x w, Y n x w), C(z) = C - z [I_n; 0], but X
+ * and Y are DEVICE column-major complex arrays with leading dimensions ldx,
+ * ldy (in complex elements), owned by the caller, and the call only
+ * enqueues the work on the handle's stream (Y is valid once that stream has
+ * reached this point).  Its workspace (the dense split-K partial products
+ * and a small header) is a static 32 MiB device array, one per GPU, set up
+ * by ps_create; it calls no hipMalloc / hipFree and no allocating library
+ * routine.  Limits: 1 <= w <= 64 and, for dense C, rows(Y) * w * 16 bytes
+ * <= 32 MiB - 256.  All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (different handles or streams) race and must
+ * be serialised by the caller.  Errors: PS_EINVAL (NULL pointers, w, ld or
+ * size out of range, non-finite z), PS_EDEVICE. */
+ps_status ps_apply_noalloc(ps_matrix* h, int32_t herm, double z_re, double z_im, const double* X,
+                           int64_t ldx, int32_t w, double* Y, int64_t ldy);
 
 #ifdef __cplusplus
 }

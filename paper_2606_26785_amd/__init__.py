@@ -115,6 +115,9 @@ def load():
     lib.ps_debug_store.restype = ctypes.c_int
     lib.ps_debug_ritz.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P, P]
     lib.ps_debug_ritz.restype = ctypes.c_int
+    lib.ps_apply_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                     ctypes.c_int32, P, ctypes.c_int64]
+    lib.ps_apply_noalloc.restype = ctypes.c_int
     lib.ps_debug_order.argtypes = [ctypes.c_int32] * 6 + [P, P]
     lib.ps_debug_order.restype = ctypes.c_int
     lib.ps_debug_norm.argtypes = [P]
@@ -272,6 +275,16 @@ def debug_apply(mat: Matrix, X: np.ndarray, z: complex = 0j, herm: bool = False)
     _check(load().ps_debug_apply(mat.handle, int(herm), float(np.real(z)), float(np.imag(z)), _ptr(X), w,
                                  _ptr(Y)), "ps_debug_apply")
     return Y
+
+
+def apply_noalloc(mat: Matrix, X_ptr: int, ldx: int, w: int, Y_ptr: int, ldy: int, z: complex = 0j,
+                  herm: bool = False) -> None:
+    """Y = C(z) X or C(z)^* X on device arrays (integer device addresses,
+    column-major, leading dimensions in complex elements); only enqueues the
+    work on the handle's stream and allocates nothing."""
+    _check(load().ps_apply_noalloc(mat.handle, int(herm), float(np.real(z)), float(np.imag(z)),
+                                   ctypes.c_void_p(int(X_ptr)), int(ldx), int(w), ctypes.c_void_p(int(Y_ptr)),
+                                   int(ldy)), "ps_apply_noalloc")
 
 
 def debug_order(nx: int, ny: int, tx: int, ty: int, b: int, traversal: int):

@@ -276,8 +276,10 @@ struct Engine {
 
     // ---- operator applies on tiles (columns w per tile)
     // Y (m rows) = C(z) X (n rows);  herm: Y (n rows) = C(z)^* X (m rows)
+    // ws / ws_n: a caller-provided workspace for the dense split-K partials
+    // (default: the handle's own apply_ws)
     void apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xstride, int64_t ldx, zd* Y,
-               int64_t ystride, int64_t ldy, int w, const zd* dz);
+               int64_t ystride, int64_t ldy, int w, const zd* dz, zd* ws = nullptr, size_t ws_n = 0);
 
     // pinned staging ring for host-to-device uploads: every upload copies its
     // bytes into a fresh slice, so an upload never waits for the stream (the

@@ -339,8 +339,9 @@ void Engine::orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, 
 
 // ---------------------------------------------------------------------------
 void Engine::apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xstride, int64_t ldx, zd* Y,
-                   int64_t ystride, int64_t ldy, int w, const zd* dz)
+                   int64_t ystride, int64_t ldy, int w, const zd* dz, zd* ws, size_t ws_n)
 {
+    if (!ws) { ws = apply_ws.p; ws_n = apply_ws.n; }
     if (nt <= 0) return;
     stats.mv_M += (int64_t)nt * w;
     if (op.kind == PS_DENSE) {
@@ -360,10 +361,10 @@ void Engine::apply(bool herm, const int* dlist, int nt, const zd* X, int64_t xst
         a.z = dz;
         a.conjz = herm ? 1 : 0;
         a.nshift = op.n;
-        a.part = apply_ws.p;
+        a.part = ws;
         int64_t N = (int64_t)nt * w;
-        if (apply_ws.n < (size_t)a.m * N) throw DeviceError("operator-apply workspace too small");
-        a.splitk = (int)std::max<int64_t>(1, (int64_t)(apply_ws.n / ((size_t)a.m * N)));
+        if (ws_n < (size_t)a.m * N) throw DeviceError("operator-apply workspace too small");
+        a.splitk = (int)std::max<int64_t>(1, (int64_t)(ws_n / ((size_t)a.m * N)));
         int pi = prof.begin(st, 0, 8.0 * a.m * a.K * N, 16.0 * ((double)a.m * a.K + (double)a.K * N + (double)a.m * N));
         launch_dense_apply(a, st);
         prof.end(st, pi);

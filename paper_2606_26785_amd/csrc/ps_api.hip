@@ -1,6 +1,7 @@
 // C ABI (include/ps.h): argument checking, handle lifecycle, error mapping.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -8,7 +9,48 @@
 
 struct ps_matrix {
     Engine eng;
+    int dev = 0;       // device current at ps_create
 };
+
+// Workspace of ps_apply_noalloc: one copy of this array per GPU, resident
+// until the process ends.  Host code never uses the array's name as an
+// address: scratch_setup() takes each device's own address once, with that
+// device current, and the entry point passes that address to its kernels.
+// Layout: bytes [0, 256) hold the one-item tile list and z; the dense
+// split-K partial products follow.
+#define PS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+#define PS_NOALLOC_HEADER 256
+static __device__ __align__(256) unsigned char scratch[PS_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[256];      // per device ordinal
+
+static hipError_t scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[dev] = ptr;
+    return e;
+}
+
+static void* scratch_ptr(int dev)
+{
+    if (dev < 0 || dev >= 256) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+// writes the one-item tile list and z into the scratch header (a kernel, not
+// a memset or host copy, so that the call can be captured into a graph)
+__global__ void k_noalloc_header(int* list, zd* z, double zr, double zi)
+{
+    if (threadIdx.x == 0) {
+        list[0] = 0;
+        z[0] = zmake(zr, zi);
+    }
+}
 
 static thread_local std::string g_last_error;
 
@@ -116,6 +158,11 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
     }
     ps_matrix* h = new (std::nothrow) ps_matrix();
     if (!h) return fail(PS_ENOMEM, "host allocation failed");
+    if (hipGetDevice(&h->dev) != hipSuccess || scratch_setup(h->dev) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return fail(PS_EDEVICE, "no usable device (static workspace address)");
+    }
     try {
         h->eng.create(d, &p, (hipStream_t)hip_stream);
     } catch (const InvalidArg& e) {
@@ -211,6 +258,43 @@ extern "C" ps_status ps_debug_apply(ps_matrix* h, int32_t herm, double z_re, dou
     } catch (const std::exception& e) {
         return fail(PS_EDEVICE, e.what());
     }
+}
+
+extern "C" ps_status ps_apply_noalloc(ps_matrix* h, int32_t herm, double z_re, double z_im, const double* X,
+                                      int64_t ldx, int32_t w, double* Y, int64_t ldy)
+{
+    if (!h || !X || !Y) return fail(PS_EINVAL, "NULL argument");
+    if (w < 1 || w > 64) return fail(PS_EINVAL, "w must be 1..64");
+    if (!std::isfinite(z_re) || !std::isfinite(z_im)) return fail(PS_EINVAL, "non-finite z");
+    Engine& E = h->eng;
+    const int64_t rin = herm ? E.m : E.n, rout = herm ? E.n : E.m;
+    if (ldx < rin || ldy < rout) return fail(PS_EINVAL, "ldx or ldy below the row count");
+    const size_t part_need = (E.op.kind == PS_DENSE) ? (size_t)rout * w * sizeof(zd) : 0;
+    if (PS_NOALLOC_HEADER + part_need > PS_NOALLOC_SCRATCH_BYTES)
+        return fail(PS_EINVAL, "rows x w exceed the static workspace (32 MiB: rows * w * 16 bytes <= 32 MiB - 256)");
+    char* base = (char*)scratch_ptr(h->dev);
+    if (!base) return fail(PS_EDEVICE, "static workspace not set up on this device");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(PS_EDEVICE, "hipGetDevice failed");
+    if (cur != h->dev && hipSetDevice(h->dev) != hipSuccess) return fail(PS_EDEVICE, "hipSetDevice failed");
+    ps_status rc = PS_OK;
+    const bool prof_on = E.prof.on;
+    try {
+        E.prof.on = false;     // no profiling events (they are created on demand)
+        int* dl = (int*)base;
+        zd* dz = (zd*)(base + 16);
+        zd* part = (zd*)(base + PS_NOALLOC_HEADER);
+        const size_t part_n = (PS_NOALLOC_SCRATCH_BYTES - PS_NOALLOC_HEADER) / sizeof(zd);
+        hipLaunchKernelGGL(k_noalloc_header, dim3(1), dim3(64), 0, E.st, dl, dz, z_re, z_im);
+        HIPCHK(hipGetLastError());
+        E.apply(herm != 0, dl, 1, (const zd*)X, 0, ldx, (zd*)Y, 0, ldy, w, dz, part, part_n);
+        HIPCHK(hipGetLastError());
+    } catch (const std::exception& e) {
+        rc = fail(PS_EDEVICE, e.what());
+    }
+    E.prof.on = prof_on;
+    if (cur != h->dev) (void)hipSetDevice(cur);
+    return rc;
 }
 
 extern "C" ps_status ps_debug_order(int32_t nx, int32_t ny, int32_t tx, int32_t ty, int32_t b, int32_t traversal,
