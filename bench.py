@@ -39,12 +39,13 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix cores and vector units alike)
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = ["operator_apply", "precond_apply", "ritz_extraction", "factorization_gemm_wide",
+CLASS_NAMES = ["operator_apply", "precond_apply", "ritz_extraction", "factorization_gemm",
                "factorization_diag", "small_per_tile", "tall_skinny", "other", "factorization_gemm_narrow"]
 CLASS_BOUND = ["mfma", "mfma", "alu", "mfma", "alu", "alu", "hbm", "hbm", "mfma"]
 CLASS_KERNELS = ["k_dense_gemm + k_dense_reduce (dense) or k_csr_apply (CSR)", "k_zgemm (+ k_zgemm_reduce)",
-                 "k_ritz", "k_zgemm_wide", "k_chol_step, k_form_normal", "k_rr_hl, k_chol_dd, k_svqb, k_rotations",
-                 "k_gram_part, k_gemm_ts, k_colnorm_part", "copies, fills", "k_zgemm_fact (+ k_zgemm_reduce)"]
+                 "k_ritz", "k_zgemm_fact64", "k_chol_step, k_form_normal",
+                 "k_rr_hl, k_chol_dd, k_svqb, k_rotations", "k_gram_part, k_gemm_ts, k_colnorm_part",
+                 "copies, fills", "k_zgemm_fact (+ k_zgemm_reduce)"]
 
 
 def path_work(st, n, r, k):
@@ -93,7 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--budget-s", type=float, default=500.0,
                     help="wall-clock budget of the whole run (timed steps stop when the next would not fit)")
-    ap.add_argument("--workload", default="toeplitz", choices=["toeplitz", "convdiff", "serving"],
+    ap.add_argument("--workload", default="toeplitz", choices=["toeplitz", "convdiff", "serving", "batched"],
                     help="toeplitz: dense Toeplitz n=4000, 200x200 (default); convdiff: sparse CSR n=250,000, "
                          "100x100; serving: a Poisson stream of mixed requests (reduced sizes, see --serve-*)")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -102,6 +103,11 @@ def main():
     ap.add_argument("--serve-dense", default="256,1024", help="dense n range (full stream: 256,4096)")
     ap.add_argument("--serve-sparse", default="40,100", help="stencil side N range (full stream: 100,447)")
     ap.add_argument("--serve-grid", default="16,32", help="grid side range (full stream: 32,128)")
+    ap.add_argument("--batch-dense", type=int, default=24, help="batched: dense matrices (full batch: 192)")
+    ap.add_argument("--batch-fold", type=int, default=8, help="batched: rectangular foldings (full batch: 64)")
+    ap.add_argument("--batch-dense-n", default="64,512", help="batched: dense n range (full batch: 64,1024)")
+    ap.add_argument("--batch-fold-n", default="1000,4000", help="batched: folding n range (full: 1000,20000)")
+    ap.add_argument("--batch-grid", type=int, default=16, help="batched: grid side (full batch: 64)")
     ap.add_argument("--n", type=int, default=4000)
     ap.add_argument("--grid", type=int, default=200)
     ap.add_argument("--plain-stride", type=int, default=10,
@@ -113,6 +119,7 @@ def main():
     ap.add_argument("--tiles-x", type=int, default=0)
     ap.add_argument("--tiles-y", type=int, default=0)
     ap.add_argument("--batch", type=int, default=20)
+    ap.add_argument("--precond", type=int, default=-1, help="ps_params.precond (-1: the library default)")
     ap.add_argument("--save-sigma", default="", help="write the grid's sigma and flags to this .npy")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-mebibyte device buffer 4 times and exit (the known-size copy that "
@@ -146,14 +153,17 @@ def main():
         return
     if args.workload == "serving":
         return serve_main(args, log)
+    if args.workload == "batched":
+        return batched_main(args, log)
     if args.workload == "convdiff":
         wl = workloads.convection_diffusion()
         params = P.default_params(profile=args.profile, verbose=0 if args.quiet else 1, tiles_x=args.tiles_x,
-                                  tiles_y=args.tiles_y, batch=args.batch, k_max=64, tile_mem_gb=96)
+                                  tiles_y=args.tiles_y, batch=args.batch, k_max=64, tile_mem_gb=96,
+                                  precond=args.precond)
     else:
         wl = workloads.toeplitz_band(n=args.n, grid=args.grid)
         params = P.default_params(profile=args.profile, verbose=0 if args.quiet else 1, tiles_x=args.tiles_x,
-                                  tiles_y=args.tiles_y, batch=args.batch)
+                                  tiles_y=args.tiles_y, batch=args.batch, precond=args.precond)
     npts = wl.npts
     t0 = time.perf_counter()
     mat = P.create_from_workload(wl, params=params)
@@ -212,6 +222,8 @@ def main():
                     "launches": int(launches), "avg_launch_ms": avg_ms, "flops_per_launch": fl,
                     "bytes_per_launch": by,
                     "device_ms_by_class": {CLASS_NAMES[i]: kms[i] for i in range(len(kms)) if kms[i] > 0},
+                    "launches_by_class": {CLASS_NAMES[i]: int(st["k_launches"][i]) for i in range(len(kms))
+                                          if kms[i] > 0},
                     "frac_by_class": {CLASS_NAMES[i]: (st["k_flops"][i] / (kms[i] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
                                                        if CLASS_BOUND[i] != "hbm" else
                                                        st["k_bytes"][i] / (kms[i] * 1e-3) / 1e9 / PEAK_HBM_GBS)
@@ -333,11 +345,16 @@ def main():
         "config": {"workload": ("dense-toeplitz-n%d-grid%dx%d" if args.workload == "toeplitz" else
                                 "csr-convdiff-n%d-grid%dx%d") % (wl.n, wl.nx, wl.ny), "n": wl.n,
                    "grid": [wl.nx, wl.ny], "r": params.r, "k_max": params.k_max, "points": npts,
-                   "precond": "base (exact Cholesky sites)" if wl.kind == "dense" else
-                              "two-level (incomplete LU base + recycled projection subspace)"},
+                   "precond": {0: "none (K = I)", 1: "base (exact Cholesky sites)" if wl.kind == "dense" else
+                               "base (incomplete Cholesky sites)",
+                               2: "two-level (%s base + recycled projection subspace)" % (
+                                   "regularised Cholesky" if wl.kind == "dense" else
+                                   "incomplete Cholesky of N(z_dag)")}[params.precond if params.precond >= 0 else
+                                                                        (1 if wl.kind == "dense" else 2)]},
         "stats": {k: st[k] for k in ("accepted", "refined", "uncertified", "certified", "lipschitz_redo",
                                      "lobpcg_iters", "precond_iters", "ritz_jobs", "store_updates", "rebuilds",
-                                     "cert_tests", "repairs", "rounds", "mv_M", "sv_F", "t_ritz_ms",
+                                     "cert_tests", "repairs", "rounds", "mv_M", "sv_F", "proj_accepted",
+                                     "proj_refined", "proj_iters", "ic_retries", "t_ritz_ms",
                                      "t_lobpcg_ms", "t_update_ms", "t_precond_ms")},
         "parity": parity,
         "create_s": t_create,
@@ -414,6 +431,58 @@ def serve_main(args, log):
         "uncertified": unc,
         "peak_active": srv.peak_active,
         "peak_footprint_gb": srv.peak_bytes / 1e9,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batched_main(args, log):
+    """Batched uneven matrices: every matrix of the batch arrives at once and
+    the serving loop runs them with continuous batching (one handle and HIP
+    stream each, up to --serve-max-active at a time, admission by device
+    memory).  Reports grid points/s over the whole batch."""
+    import torch
+    import workloads
+    from paper_2606_26785_amd import serving
+
+    rng2 = lambda s: tuple(int(x) for x in s.split(","))
+    wls = workloads.batched_uneven(seed=1004, n_dense=args.batch_dense, n_fold=args.batch_fold,
+                                   grid=args.batch_grid, dense_range=rng2(args.batch_dense_n),
+                                   fold_range=rng2(args.batch_fold_n))
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    be = serving.LibraryBackend()
+    be.run(serving.Request(-1, workloads.triangular_disk(seed=1, n=64, grid=4), 0.0))
+    log("batch of %d matrices (%d dense, %d foldings), grid %dx%d" % (
+        len(wls), args.batch_dense, args.batch_fold, args.batch_grid, args.batch_grid))
+    srv = serving.Server(be, hbm_budget=budget, max_active=args.serve_max_active)
+    reqs = [serving.Request(i, wl, 0.0) for i, wl in enumerate(wls)]
+    t0 = time.perf_counter()
+    res = srv.run(reqs, time_limit=args.budget_s)
+    span = time.perf_counter() - t0
+    pts = sum(wl.npts for wl in wls)
+    unc = sum(int(r.stats["uncertified"]) for r in res)
+    out = {
+        "metric": "batched sigma_min grid pts/s (uneven dense and rectangular CSR matrices, continuous batching)",
+        "value": pts / span,
+        "unit": "pts/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": span * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic (seeded uneven batch: dense triangular and rectangular banded foldings)",
+        "config": {"workload": "batched-uneven-%d" % len(wls), "dense": args.batch_dense,
+                   "dense_n": args.batch_dense_n, "foldings": args.batch_fold, "folding_n": args.batch_fold_n,
+                   "grid": args.batch_grid, "max_active": args.serve_max_active,
+                   "reduced": "from 192 dense (n 64..1024) + 64 foldings (n 1000..20000) on 64 x 64 grids"},
+        "points": pts,
+        "uncertified": unc,
+        "peak_active": srv.peak_active,
         "roofline": None,
         "cpu_baseline": None,
     }

@@ -21,7 +21,8 @@
  *    an exact Cholesky factor at sites z_dag placed by a base-only form of
  *    the rebuild rule (eq. (tauRecycle) with the projection part empty);
  *  - 2 (square CSR default): the two-level preconditioner of eq.
- *    (twolevel): an incomplete-LU base (CSR) or a regularised Cholesky base
+ *    (twolevel): an incomplete-Cholesky base of N(z_dag) (CSR) or a
+ *    regularised Cholesky base
  *    (dense), plus a projection subspace recycled by Alg. 4 (recyProj) and
  *    eq. (tolTz), refined by LOBPCG-SVD on Mbar(z) = C(z) F^{-1} when the
  *    test fails, and the full rebuild rule of eq. (tauRecycle);
@@ -108,9 +109,12 @@ typedef struct {
                            (Alg. 4 and 5), K = F^* F with F the Cholesky
                            factor of N(z_dag) + (reg_base (||C|| + |z_dag|))^2 I,
                            rebuilt by the rule of eq. (tauRecycle);
-                           For a square CSR C, F is instead the incomplete
-                           LU factor (no fill) of C - z_dag I in a colour
-                           ordering of its graph, K = (F P)^* (F P).
+                           For a square CSR C, K = L D L^* is instead the
+                           incomplete Cholesky factorization (no fill, on
+                           the pattern of C^* C in a colour ordering of its
+                           graph) of N(z_dag) + alpha I, alpha starting at
+                           (reg_base (||C|| + |z_dag|))^2 and raised 4x
+                           until every pivot is positive; F = D^{1/2} L^* P.
                            -1 (default): 1 for dense C, 2 for square CSR,
                            0 for rectangular CSR */
     int32_t tiles_x;    /* grid-front partition: tiles along x (0 = auto) */
@@ -120,7 +124,8 @@ typedef struct {
                            (default 48) */
     int32_t site_mem_gb;/* device memory for preconditioner sites and their
                            staging (dense: explicit inverse factors; sparse:
-                           incomplete-LU values and projection stores)
+                           incomplete-Cholesky values and projection
+                           stores)
                            (default 128) */
     int32_t batch;      /* b of the batch-zigzag traversal (default 20) */
     int32_t traversal;  /* order of the points inside a tile: 0 batch zigzag
@@ -169,8 +174,10 @@ typedef struct {
                            before starting LOBPCG (default 0: on the dense
                            Toeplitz workload half of those tests fail and the
                            sweep is 27% slower) */
-    double reg_base;    /* precond = 2: relative regularisation of the base
-                           preconditioner, which bounds gamma = ||F^{-1}|| by
+    double reg_base;    /* relative regularisation of the base
+                           preconditioner (dense with precond = 2, and the
+                           starting shift of the sparse incomplete
+                           Cholesky), which bounds gamma = ||F^{-1}|| by
                            1 / (reg_base (||C|| + |z_dag|)) so that a site
                            serves a region even near the spectrum (0.02) */
     int32_t lipschitz;  /* 1 (default): after the sweep, points whose value
@@ -178,6 +185,13 @@ typedef struct {
                            neighbour (the norm of C(z) on the neighbour's
                            singular vector, or the 1-Lipschitz bound) are
                            refined again from a random start */
+    int32_t fact_blas;  /* dense base sites and inertia tests: 1 runs the
+                           plain products of the blocked Cholesky (the
+                           rank-128 trailing Hermitian updates and the F^{-1}
+                           block products) as rocBLAS strided-batched
+                           ZHERK / ZGEMM; 0 (default) on this library's
+                           matrix-core kernels, which are faster on these
+                           shapes */
 } ps_params;
 
 typedef struct {
@@ -206,22 +220,23 @@ typedef struct {
     int64_t repairs;       /* LOBPCG steps whose search space lost rank and was rebuilt */
     int64_t mv_update;     /* operator column-applies made by updateRecy (3 r per
                               singular update with S = [I_n; 0]: C Q, C^* C Q, C^* S Q) */
+    int64_t ic_retries;    /* sparse sites refactored with a 4x larger shift after a
+                              non-positive incomplete-Cholesky pivot */
     double t_total_ms;     /* wall time of ps_eval */
     double t_ritz_ms, t_lobpcg_ms, t_update_ms, t_precond_ms;
     /* with profile >= 1: event-timed kernel classes (launches, device ms,
      * algorithmic flops and bytes per class).  Class 0: operator applies
      * C X, C^* Y (dense: matrix-core GEMM + split-K reduction; CSR: SpMM);
      * class 1: preconditioner applies K^{-1} W; class 2: Ritz extraction
-     * (per-point QR + Jacobi SVD + residual); class 3: the large
-     * matrix-core products inside factorizations (preconditioner sites,
-     * inertia tests: trailing updates and the F^{-1} block columns, on the
-     * 128 x 64-tile kernel); class 4: the diagonal-block steps of those
-     * factorizations and the forming of N(z); class 8: the narrow
-     * matrix-core products inside factorizations (row updates and diagonal
-     * F^{-1} blocks).  With profile >= 2 also class 5: per-tile small dense
-     * kernels (Rayleigh-Ritz-SVD, Cholesky of Gram matrices, SVQB,
-     * rotations); class 6: tall-skinny Gram, product and norm kernels;
-     * class 7: the rest (copies, fills). */
+     * (per-point QR + Jacobi SVD + residual); class 3: matrix-core products
+     * at least 64 columns wide inside factorizations (preconditioner sites,
+     * inertia tests: the trailing updates and the F^{-1} block columns, on
+     * 64 x 64 tiles); class 4: the diagonal-block steps of those
+     * factorizations and the forming of N(z); class 8: the narrower
+     * products inside factorizations (64 x 32 tiles).  With profile >= 2
+     * also class 5: per-tile small dense kernels (Rayleigh-Ritz-SVD,
+     * Cholesky of Gram matrices, SVQB, rotations); class 6: tall-skinny
+     * Gram, product and norm kernels; class 7: the rest (copies, fills). */
     int64_t k_launches[PS_NCLASS];
     double k_ms[PS_NCLASS];
     double k_flops[PS_NCLASS];

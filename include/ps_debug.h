@@ -39,6 +39,15 @@ ps_status ps_debug_twolevel(ps_matrix* h, double zd_re, double zd_im, double z_r
  * last ps_debug_twolevel call. */
 ps_status ps_debug_site(ps_matrix* h, double* dreg, double* gamma);
 
+/* Build the sparse base site at z (square CSR handle with a
+ * preconditioner): K = F^* F the incomplete Cholesky factorization of
+ * N(z) + alpha I (Sec. 3 and 4), and return Y = F^{-1} X (trans 0) or
+ * Y = F^{-*} X (trans 1) for host column-major n x w X (w <= 64), with the
+ * shift alpha used.  Errors: PS_EINVAL, PS_EUNSUPPORTED (dense handle or
+ * no preconditioner), PS_EDEVICE. */
+ps_status ps_debug_sparse_site(ps_matrix* h, double z_re, double z_im, int32_t trans, const double* X, int32_t w,
+                               double* Y, double* alpha);
+
 /* The recycled singular store of `tile` as the last ps_eval left it (Sec.
  * 2.2): its dimension k, the orthonormal basis V (n x k_max), W1 = C V
  * (m x k_max), W3 = C^* C V and W4 = C^* S V (n x k_max), and the cached R

@@ -52,7 +52,8 @@ class ps_params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("eta_abs", ctypes.c_double), ("rho_small", ctypes.c_double),
                 ("profile", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("tol_abs", ctypes.c_double), ("esc_iters", ctypes.c_int32),
-                ("cert_recycled", ctypes.c_int32), ("reg_base", ctypes.c_double), ("lipschitz", ctypes.c_int32)]
+                ("cert_recycled", ctypes.c_int32), ("reg_base", ctypes.c_double), ("lipschitz", ctypes.c_int32),
+                ("fact_blas", ctypes.c_int32)]
 
 
 class ps_stats(ctypes.Structure):
@@ -60,7 +61,7 @@ class ps_stats(ctypes.Structure):
         "points", "accepted", "refined", "uncertified", "lobpcg_iters", "proj_accepted",
         "proj_refined", "proj_iters", "rebuilds", "mv_M", "sv_F", "rounds", "certified", "lipschitz_redo",
         "guard_rejects", "cert_tests", "builds_shared", "builds_private", "ritz_jobs", "store_updates",
-        "precond_iters", "repairs", "mv_update")] + \
+        "precond_iters", "repairs", "mv_update", "ic_retries")] + \
         [(n, ctypes.c_double) for n in ("t_total_ms", "t_ritz_ms", "t_lobpcg_ms", "t_update_ms",
                                         "t_precond_ms")] + \
         [("k_launches", ctypes.c_int64 * NCLASS), ("k_ms", ctypes.c_double * NCLASS),
@@ -120,6 +121,9 @@ def load():
     lib.ps_apply_noalloc.restype = ctypes.c_int
     lib.ps_debug_order.argtypes = [ctypes.c_int32] * 6 + [P, P]
     lib.ps_debug_order.restype = ctypes.c_int
+    lib.ps_debug_sparse_site.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, ctypes.c_int32,
+                                         P, P]
+    lib.ps_debug_sparse_site.restype = ctypes.c_int
     lib.ps_debug_norm.argtypes = [P]
     lib.ps_debug_norm.restype = ctypes.c_double
     _lib = lib
@@ -285,6 +289,17 @@ def apply_noalloc(mat: Matrix, X_ptr: int, ldx: int, w: int, Y_ptr: int, ldy: in
     _check(load().ps_apply_noalloc(mat.handle, int(herm), float(np.real(z)), float(np.imag(z)),
                                    ctypes.c_void_p(int(X_ptr)), int(ldx), int(w), ctypes.c_void_p(int(Y_ptr)),
                                    int(ldy)), "ps_apply_noalloc")
+
+
+def debug_sparse_site(mat: Matrix, z: complex, X: np.ndarray, trans: int = 0):
+    """(Y, alpha): Y = F^{-1} X (trans 0) or F^{-*} X (trans 1) for the
+    sparse base site built at z (test hook)."""
+    X = np.asfortranarray(X, dtype=np.complex128)
+    Y = np.empty_like(X)
+    a = np.zeros(1)
+    _check(load().ps_debug_sparse_site(mat.handle, float(np.real(z)), float(np.imag(z)), int(trans), _ptr(X),
+                                       X.shape[1], _ptr(Y), _ptr(a)), "ps_debug_sparse_site")
+    return Y, float(a[0])
 
 
 def debug_order(nx: int, ny: int, tx: int, ty: int, b: int, traversal: int):

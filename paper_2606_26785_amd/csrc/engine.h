@@ -76,8 +76,9 @@ struct Operator {
     DBuf<int32_t> ci, ciH;
     DBuf<zd> v, vH;
     double normC = 0.0;                 // ||C||_2 estimate (power iteration, x1.01)
-    // colour-ordered pattern for the incomplete LU base preconditioner (square CSR)
-    DBuf<int64_t> sp_rp, sp_src, sp_diag, sp_rpT, sp_mapT;
+    // colour-ordered pattern of N = C^* C for the incomplete Cholesky base
+    // preconditioner (square CSR)
+    DBuf<int64_t> sp_rp, sp_diag, sp_rpT, sp_mapT, sp_ccp, sp_ca, sp_cb;
     DBuf<int32_t> sp_ci, sp_ciT;
     DBuf<int> sp_perm;
     std::vector<int64_t> sp_cptr;
@@ -116,6 +117,7 @@ struct KProf {
 
 struct Engine {
     hipStream_t st = nullptr;
+    void* blas = nullptr;      // rocBLAS handle on st (dense sites with fact_blas)
     ps_params P{};
     Operator op;
 
@@ -248,11 +250,12 @@ struct Engine {
     // Ebar and Lambda_bar; acc[i] = 1 when eq. (tolTz) holds
     void recy_proj(const std::vector<int>& L, std::vector<char>& acc);
     void upload_pk();
-    // sparse sites: incomplete LU values per slot, site points, work blocks
+    // sparse sites: incomplete Cholesky values per slot, site points, work blocks
     DBuf<zd> Slu, Svec, pS, d_slotz, Tq;
     DBuf<int> d_listC;
-    DBuf<int> d_nfloor;
-    int64_t ilu_floors = 0;
+    DBuf<int> d_icbad;          // per slot: a pivot of its incomplete Cholesky was not positive
+    DBuf<double> d_alpha;       // per slot: diagonal shift alpha of N(z_dag) + alpha I
+    std::vector<double> slot_alpha;
     void build_sparse_pattern();        // colouring and patterns (host, once per handle)
     std::vector<int> build_sparse_sites(const std::vector<zd>& sites, const std::vector<int>& slots);
     bool site_at(int t) const;                   // the tile's site was built at its current point
@@ -262,9 +265,16 @@ struct Engine {
     // whose projection refinement then runs (phase 1); fl gets the rebuild flag
     void rebuild_here(const std::vector<int>& tl, std::vector<uint8_t>& fl);
 
+    // plain products inside the blocked Cholesky of the dense sites (list =
+    // staging positions 0 .. nb-1): rocBLAS strided-batched ZHERK (upper,
+    // A == B) / ZGEMM when fact_blas, else zgemm()
+    void fact_gemm(const int* dl, int nb, int64_t M, int64_t N, int64_t Kd, const zd* A, int64_t lda, int64_t sA,
+                   int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
+                   double beta, int upper = 0, int tri = 0);
+    ~Engine();
+
     KProf prof;
     int zgemm_cls = 1;        // profiling class of zgemm launches (3 inside factorizations)
-    bool use_wide = true;     // 128 x 64-tile kernel for large products
     ps_stats stats{};
     std::vector<Tile> tiles;
     std::vector<zd> zs;       // grid points of the current eval

@@ -587,7 +587,7 @@ void Engine::size_for(int tiles)
         d_shift.alloc(NBLD); d_notpd.alloc(NBLD);
         zgemm_ws.alloc(std::max<size_t>((size_t)32 << 20, t * (size_t)n * r * 16));
     } else if (use_prec) {
-        // incomplete LU sites: values, power-iteration vectors, solve work;
+        // incomplete Cholesky sites: values, power-iteration vectors, solve work;
         // the projection stores (8 n x kbar blocks per site) bound the count
         NBLD = 8;
         const double per = 16.0 * ((double)op.spat.nnz + 4.0 * n + (two_level ? 9.0 : 1.0) * n * P.kbar_max);
@@ -596,7 +596,9 @@ void Engine::size_for(int tiles)
         Svec.alloc((size_t)NS * 4 * n);
         pS.alloc((size_t)NS * n * std::max(P.kbar_max, 1));
         d_slotz.alloc(NS);
-        d_nfloor.alloc(1);
+        d_icbad.alloc(NS);
+        d_alpha.alloc(NS);
+        slot_alpha.assign(NS, 0.0);
         Tq.alloc(t * n * r);
         d_listC.alloc(std::max<size_t>(t, NS));
         std::vector<zd> z0((size_t)NS, zmake(0.0, 0.0));

@@ -2,6 +2,8 @@
 // z_dag and application K^{-1} W = F^{-1} F^{-*} W.
 #include "engine.h"
 
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -55,17 +57,60 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
     double fl = 8.0 * (double)M * ncols * Kd * ((upper || tri) ? 0.5 : 1.0);
     double by = 16.0 * ((double)nt * M * Kd * (tri ? 0.5 : 1.0) + (double)Kd * ncols +
                         (double)M * ncols * (beta != 0.0 ? 2.0 : 1.0));
-    const bool wide = use_wide && !gmap && M >= 128 && N >= 64 && Kd >= 32;
-    // inside factorizations: class 3 for the wide kernel, 8 for the narrow one
-    int pi = prof.begin(st, (zgemm_cls == 3 && !wide) ? 8 : zgemm_cls, fl, by);
-    if (wide) {
-        // large products: wide tiles fill the chip without splitting K
-        a.splitk = 1;
-        launch_zgemm_wide(a, nt, st);
+    // inside factorizations: class 3 for the 64 x 64-tile kernel (products
+    // at least 64 columns wide), 8 for the narrower ones
+    const int cls = (zgemm_cls == 3 && (gmap || N < 64)) ? 8 : zgemm_cls;
+    int pi = prof.begin(st, cls, fl, by);
+    launch_zgemm(a, nt, st, zgemm_cls == 3 ? 2 : 0);
+    prof.end(st, pi);
+}
+
+void Engine::fact_gemm(const int* dl, int nb, int64_t M, int64_t N, int64_t Kd, const zd* A, int64_t lda, int64_t sA,
+                       int opA, const zd* Bm, int64_t ldb, int64_t sB, zd* Cm, int64_t ldc, int64_t sC, double alpha,
+                       double beta, int upper, int tri)
+{
+    if (!P.fact_blas) {
+        zgemm(dl, nb, M, N, Kd, A, lda, sA, opA, Bm, ldb, sB, Cm, ldc, sC, alpha, beta, upper, tri);
+        return;
+    }
+    if (nb <= 0 || M <= 0 || N <= 0) return;
+    if (!blas) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) throw DeviceError("rocblas_create_handle failed");
+        blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)blas;
+    if (rocblas_set_stream(h, st) != rocblas_status_success) throw DeviceError("rocblas_set_stream failed");
+    const double fl = 8.0 * (double)M * N * Kd * nb * ((upper || tri) ? 0.5 : 1.0);
+    const double by = 16.0 * nb * ((double)M * Kd * (tri ? 0.5 : 1.0) + (double)Kd * N +
+                                   (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
+    const int pi = prof.begin(st, zgemm_cls, fl, by);
+    rocblas_status rs;
+    if (upper && Kd > 0) {
+        // C = alpha A^* A + beta C on the upper triangle (A == B, A stored Kd x M)
+        if (opA != 1 || A != Bm || M != N) throw DeviceError("fact_gemm: Hermitian update needs C = A^* A");
+        rs = rocblas_zherk_strided_batched(h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, (rocblas_int)M,
+                                           (rocblas_int)Kd, &alpha, (const rocblas_double_complex*)A, (rocblas_int)lda,
+                                           (rocblas_stride)sA, &beta, (rocblas_double_complex*)Cm, (rocblas_int)ldc,
+                                           (rocblas_stride)sC, (rocblas_int)nb);
     } else {
-        launch_zgemm(a, nt, st, zgemm_cls == 3 ? 1 : 0);
+        // a triangular A (tri) is stored with zeros outside its triangle
+        const rocblas_double_complex al = {alpha, 0.0}, be = {beta, 0.0};
+        rs = rocblas_zgemm_strided_batched(h, opA ? rocblas_operation_conjugate_transpose : rocblas_operation_none,
+                                           rocblas_operation_none, (rocblas_int)M, (rocblas_int)N, (rocblas_int)Kd,
+                                           &al, (const rocblas_double_complex*)A, (rocblas_int)lda, (rocblas_stride)sA,
+                                           (const rocblas_double_complex*)Bm, (rocblas_int)ldb, (rocblas_stride)sB, &be,
+                                           (rocblas_double_complex*)Cm, (rocblas_int)ldc, (rocblas_stride)sC,
+                                           (rocblas_int)nb);
     }
     prof.end(st, pi);
+    if (rs != rocblas_status_success) throw DeviceError("rocBLAS product failed");
+    (void)dl;
+}
+
+Engine::~Engine()
+{
+    if (blas) (void)rocblas_destroy_handle((rocblas_handle)blas);
 }
 
 void Engine::reset_slots()
@@ -105,7 +150,7 @@ void Engine::precond_apply(const std::vector<int>& L, const zd* W, int64_t ws, z
 {
     if (L.empty()) return;
     if (op.kind != PS_DENSE) {
-        // K^{-1} W = (F P)^{-1} (F P)^{-*} W with each tile's incomplete LU site
+        // K^{-1} W = F^{-1} F^{-*} W with each tile's incomplete Cholesky site
         finv_apply(L, 1, W, ws, n, Tn2.p, (int64_t)n * r, n);
         finv_apply(L, 0, Tn2.p, (int64_t)n * r, n, Y, ys, n);
         return;
@@ -155,7 +200,7 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
     std::vector<int> out;
     if (pd) pd->assign(sites.size(), 0);
     if (op.kind != PS_DENSE) {
-        // sparse sites: incomplete LU of C - z_dag I (shifts and inertia
+        // sparse sites: incomplete Cholesky of N(z_dag) + alpha I (shifts and inertia
         // tests are dense-only: a factorisation for a test is reported as
         // not positive definite, so no certificate is taken from it)
         if (cert_only) {
@@ -237,7 +282,7 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
                 const int kb = (int)std::min<int64_t>(PRE_NB, K1 - k0);
                 if (k0 > K0) {
                     // A[k, k0:] -= R[K0:k0, k]^* R[K0:k0, k0:]
-                    zgemm(dl, nb, kb, n - k0, k0 - K0, PN.p + K0 + k0 * n, n, nn, 1, PN.p + K0 + k0 * n, n, nn,
+                    fact_gemm(dl, nb, kb, n - k0, k0 - K0, PN.p + K0 + k0 * n, n, nn, 1, PN.p + K0 + k0 * n, n, nn,
                           PN.p + k0 + k0 * n, n, nn, -1.0, 1.0);
                 }
                 // diagonal block and row panel R[k, k1:] = R_kk^{-*} A[k, k1:] in one launch
@@ -248,22 +293,22 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
                 prof.end(st, pc);
                 if (!cert_only && k0 > K0) {
                     // F^{-1}[K0:k0, k] = -F^{-1}[K0:k0, K0:k0] R[K0:k0, k] R_kk^{-1}
-                    zgemm(dl, nb, k0 - K0, kb, k0 - K0, Fb.p + K0 + K0 * n, n, nn, 0, PN.p + K0 + k0 * n, n, nn,
+                    fact_gemm(dl, nb, k0 - K0, kb, k0 - K0, Fb.p + K0 + K0 * n, n, nn, 0, PN.p + K0 + k0 * n, n, nn,
                           T1p.p, n, (int64_t)n * PRE_NB, 1.0, 0.0);
-                    zgemm(dl, nb, k0 - K0, kb, kb, T1p.p, n, (int64_t)n * PRE_NB, 0, Dinv.p + k0, n,
+                    fact_gemm(dl, nb, k0 - K0, kb, kb, T1p.p, n, (int64_t)n * PRE_NB, 0, Dinv.p + k0, n,
                           (int64_t)n * PRE_NB, Fb.p + K0 + k0 * n, n, nn, -1.0, 0.0);
                 }
             }
             if (K1 < n) {
                 // trailing Hermitian update (upper part), rank K1 - K0
-                zgemm(dl, nb, n - K1, n - K1, K1 - K0, PN.p + K0 + K1 * n, n, nn, 1, PN.p + K0 + K1 * n, n, nn,
+                fact_gemm(dl, nb, n - K1, n - K1, K1 - K0, PN.p + K0 + K1 * n, n, nn, 1, PN.p + K0 + K1 * n, n, nn,
                       PN.p + K1 + K1 * n, n, nn, -1.0, 1.0, 1);
             }
             if (!cert_only && K0 > 0) {
                 // F^{-1}[0:K0, K] = -F^{-1}[0:K0, 0:K0] (R[0:K0, K] F^{-1}[K, K])
-                zgemm(dl, nb, K0, K1 - K0, K1 - K0, PN.p + K0 * n, n, nn, 0, Fb.p + K0 + K0 * n, n, nn, T2p.p, n,
+                fact_gemm(dl, nb, K0, K1 - K0, K1 - K0, PN.p + K0 * n, n, nn, 0, Fb.p + K0 + K0 * n, n, nn, T2p.p, n,
                       (int64_t)n * PRE_OB, 1.0, 0.0);
-                zgemm(dl, nb, K0, K1 - K0, K0, Fb.p, n, nn, 0, T2p.p, n, (int64_t)n * PRE_OB, Fb.p + K0 * n, n, nn,
+                fact_gemm(dl, nb, K0, K1 - K0, K0, Fb.p, n, nn, 0, T2p.p, n, (int64_t)n * PRE_OB, Fb.p + K0 * n, n, nn,
                       -1.0, 0.0, 0, 1);
             }
         }

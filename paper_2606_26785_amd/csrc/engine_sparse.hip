@@ -1,9 +1,10 @@
-// Sparse base preconditioner sites (square CSR C): the colour ordering and
-// patterns of the incomplete LU factorisation (host, once per handle), and
-// the construction of sites: F = ILU(0) of P (C - z_dag I) P^T, gamma =
-// ||(F P)^{-1}||_2 and lambda_n^dagger = lambda_max of the pencil
-// (N(z_dag), K) by power iteration (the quantities of the rebuild rule, eq.
-// (tauRecycle)).
+// Sparse base preconditioner sites (square CSR C): the pattern of N = C^* C,
+// its colour ordering and the contribution lists that form N(z) from the
+// values of C (host, once per handle), and the construction of sites: the
+// incomplete Cholesky factorization of N(z_dag) + alpha I (Sec. 3 and 4; the
+// shift alpha raised until every pivot is positive), gamma = ||F^{-1}||_2
+// and lambda_n^dagger = lambda_max of the pencil (N(z_dag), K) by power
+// iteration (the quantities of the rebuild rule, eq. (tauRecycle)).
 #include "engine.h"
 
 #include <algorithm>
@@ -18,76 +19,99 @@ void Engine::build_sparse_pattern()
     std::vector<int32_t> ci(op.nnz);
     HIPCHK(hipMemcpy(rp.data(), op.rp.p, sizeof(int64_t) * (m + 1), hipMemcpyDeviceToHost));
     if (op.nnz) HIPCHK(hipMemcpy(ci.data(), op.ci.p, sizeof(int32_t) * op.nnz, hipMemcpyDeviceToHost));
-    // symmetrised adjacency without the diagonal (duplicates are harmless)
-    std::vector<int64_t> deg(nn + 1, 0);
-    for (int64_t i = 0; i < nn; ++i)
+    // entries of each row of C - z I as (column, code): code = 2 q + [diagonal]
+    // for the CSR entry q, -1 for a diagonal entry C does not store
+    auto row_entries = [&](int64_t i, std::vector<std::pair<int32_t, int64_t>>& E) {
+        E.clear();
+        bool hasd = false;
         for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
-            const int64_t j = ci[q];
-            if (j == i) continue;
-            deg[i + 1]++;
-            deg[j + 1]++;
+            const bool d = (ci[q] == i);
+            hasd |= d;
+            E.push_back({ci[q], 2 * q + (d ? 1 : 0)});
         }
-    for (int64_t i = 0; i < nn; ++i) deg[i + 1] += deg[i];
-    std::vector<int32_t> adj(deg[nn]);
-    std::vector<int64_t> fill(deg.begin(), deg.end() - 1);
-    for (int64_t i = 0; i < nn; ++i)
-        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
-            const int64_t j = ci[q];
-            if (j == i) continue;
-            adj[fill[i]++] = (int32_t)j;
-            adj[fill[j]++] = (int32_t)i;
-        }
-    // greedy colouring in natural order: the smallest colour no coloured
-    // neighbour has
-    std::vector<int> color(nn, -1), stamp(64 + nn, -1);
+        if (i < nn && !hasd) E.push_back({(int32_t)i, -1});
+    };
+    // pattern of N: (j, k) for every pair of entries in one row of C, plus
+    // the diagonal
+    std::vector<std::vector<int32_t>> adj(nn);
+    std::vector<std::pair<int32_t, int64_t>> E;
+    for (int64_t i = 0; i < m; ++i) {
+        row_entries(i, E);
+        for (auto& a : E)
+            for (auto& b : E) adj[a.first].push_back(b.first);
+    }
+    for (int64_t j = 0; j < nn; ++j) {
+        adj[j].push_back((int32_t)j);
+        std::sort(adj[j].begin(), adj[j].end());
+        adj[j].erase(std::unique(adj[j].begin(), adj[j].end()), adj[j].end());
+    }
+    // greedy colouring of N's graph in natural order: the smallest colour no
+    // coloured neighbour has
+    std::vector<int> color(nn, -1), stamp(nn + 64, -1);
     int ncol = 0;
-    for (int64_t i = 0; i < nn; ++i) {
-        for (int64_t q = deg[i]; q < deg[i + 1]; ++q) {
-            const int c = color[adj[q]];
-            if (c >= 0) stamp[c] = (int)i;
+    for (int64_t j = 0; j < nn; ++j) {
+        for (int32_t k : adj[j]) {
+            const int c = color[k];
+            if (c >= 0) stamp[c] = (int)j;
         }
         int c = 0;
-        while (stamp[c] == (int)i) ++c;
-        color[i] = c;
+        while (stamp[c] == (int)j) ++c;
+        color[j] = c;
         ncol = std::max(ncol, c + 1);
     }
     // colour-major permutation (stable inside a colour)
     std::vector<int64_t> cptr(ncol + 1, 0);
-    for (int64_t i = 0; i < nn; ++i) cptr[color[i] + 1]++;
+    for (int64_t j = 0; j < nn; ++j) cptr[color[j] + 1]++;
     for (int c = 0; c < ncol; ++c) cptr[c + 1] += cptr[c];
     std::vector<int> perm(nn), iperm(nn);
     {
         std::vector<int64_t> pos(cptr.begin(), cptr.end() - 1);
-        for (int64_t i = 0; i < nn; ++i) {
-            const int64_t p = pos[color[i]]++;
-            perm[p] = (int)i;
-            iperm[i] = (int)p;
+        for (int64_t j = 0; j < nn; ++j) {
+            const int64_t p = pos[color[j]]++;
+            perm[p] = (int)j;
+            iperm[j] = (int)p;
         }
     }
-    // permuted pattern with the diagonal, columns sorted
-    std::vector<int64_t> rp2(nn + 1, 0), src2, diag2(nn);
-    std::vector<int32_t> ci2;
-    src2.reserve(op.nnz + nn);
-    ci2.reserve(op.nnz + nn);
-    std::vector<std::pair<int32_t, int64_t>> row;
+    // permuted pattern, columns sorted, diagonal positions
+    std::vector<int64_t> rp2(nn + 1, 0), diag2(nn);
+    for (int64_t p = 0; p < nn; ++p) rp2[p + 1] = rp2[p] + (int64_t)adj[perm[p]].size();
+    const int64_t nz = rp2[nn];
+    std::vector<int32_t> ci2(nz);
     for (int64_t p = 0; p < nn; ++p) {
-        const int64_t i = perm[p];
-        row.clear();
-        bool hasd = false;
-        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
-            row.push_back({iperm[ci[q]], q});
-            hasd |= (ci[q] == i);
-        }
-        if (!hasd) row.push_back({(int32_t)p, -1});
-        std::sort(row.begin(), row.end());
-        for (auto& e : row) {
-            if (e.first == p) diag2[p] = (int64_t)ci2.size();
-            ci2.push_back(e.first);
-            src2.push_back(e.second);
-        }
-        rp2[p + 1] = (int64_t)ci2.size();
+        int64_t o = rp2[p];
+        for (int32_t k : adj[perm[p]]) ci2[o++] = iperm[k];
+        std::sort(ci2.begin() + rp2[p], ci2.begin() + rp2[p + 1]);
+        for (int64_t e = rp2[p]; e < rp2[p + 1]; ++e)
+            if (ci2[e] == p) diag2[p] = e;
     }
-    const int64_t nz = (int64_t)ci2.size();
+    std::vector<std::vector<int32_t>>().swap(adj);
+    auto find_entry = [&](int64_t p, int32_t q) -> int64_t {
+        auto b = ci2.begin() + rp2[p], e = ci2.begin() + rp2[p + 1];
+        auto it = std::lower_bound(b, e, q);
+        return (int64_t)(it - ci2.begin());
+    };
+    // contribution lists: N_{jk} += conj(c_a) c_b for entries a (column j)
+    // and b (column k) of one row of C - z I
+    std::vector<int64_t> ccp(nz + 1, 0);
+    for (int64_t i = 0; i < m; ++i) {
+        row_entries(i, E);
+        for (auto& a : E)
+            for (auto& b : E) ccp[find_entry(iperm[a.first], iperm[b.first]) + 1]++;
+    }
+    for (int64_t e = 0; e < nz; ++e) ccp[e + 1] += ccp[e];
+    std::vector<int64_t> ca(ccp[nz]), cb(ccp[nz]);
+    {
+        std::vector<int64_t> fill(ccp.begin(), ccp.end() - 1);
+        for (int64_t i = 0; i < m; ++i) {
+            row_entries(i, E);
+            for (auto& a : E)
+                for (auto& b : E) {
+                    const int64_t o = fill[find_entry(iperm[a.first], iperm[b.first])]++;
+                    ca[o] = a.second;
+                    cb[o] = b.second;
+                }
+        }
+    }
     // transpose pattern: entry e' = (j, i) of the transpose maps to entry (i, j)
     std::vector<int64_t> rpT(nn + 1, 0), mapT(nz);
     std::vector<int32_t> ciT(nz);
@@ -102,28 +126,38 @@ void Engine::build_sparse_pattern()
                 mapT[o] = e;
             }
     }
-    op.sp_rp.alloc(nn + 1); op.sp_ci.alloc(nz); op.sp_src.alloc(nz); op.sp_diag.alloc(nn);
+    const int64_t nc = ccp[nz];
+    op.sp_rp.alloc(nn + 1); op.sp_ci.alloc(nz); op.sp_diag.alloc(nn);
     op.sp_rpT.alloc(nn + 1); op.sp_ciT.alloc(nz); op.sp_mapT.alloc(nz); op.sp_perm.alloc(nn);
+    op.sp_ccp.alloc(nz + 1); op.sp_ca.alloc(std::max<int64_t>(nc, 1)); op.sp_cb.alloc(std::max<int64_t>(nc, 1));
     HIPCHK(hipMemcpy(op.sp_rp.p, rp2.data(), sizeof(int64_t) * (nn + 1), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(op.sp_ci.p, ci2.data(), sizeof(int32_t) * nz, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(op.sp_src.p, src2.data(), sizeof(int64_t) * nz, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(op.sp_diag.p, diag2.data(), sizeof(int64_t) * nn, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(op.sp_rpT.p, rpT.data(), sizeof(int64_t) * (nn + 1), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(op.sp_ciT.p, ciT.data(), sizeof(int32_t) * nz, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(op.sp_mapT.p, mapT.data(), sizeof(int64_t) * nz, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(op.sp_perm.p, perm.data(), sizeof(int) * nn, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(op.sp_ccp.p, ccp.data(), sizeof(int64_t) * (nz + 1), hipMemcpyHostToDevice));
+    if (nc) {
+        HIPCHK(hipMemcpy(op.sp_ca.p, ca.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(op.sp_cb.p, cb.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice));
+    }
     op.sp_cptr = cptr;
     SparsePattern& sp = op.spat;
     sp.n = nn;
     sp.nnz = nz;
     sp.ncolors = ncol;
     sp.cptr = op.sp_cptr.data();
-    sp.rp = op.sp_rp.p; sp.ci = op.sp_ci.p; sp.src = op.sp_src.p; sp.diag = op.sp_diag.p;
+    sp.rp = op.sp_rp.p; sp.ci = op.sp_ci.p; sp.diag = op.sp_diag.p;
     sp.rpT = op.sp_rpT.p; sp.ciT = op.sp_ciT.p; sp.mapT = op.sp_mapT.p; sp.perm = op.sp_perm.p;
+    sp.ccp = op.sp_ccp.p; sp.ca = op.sp_ca.p; sp.cb = op.sp_cb.p;
 }
 
 // Factor the sites (slots[i] at sites[i]) and estimate gamma and
-// lambda_n^dagger by 12 power steps each.
+// lambda_n^dagger by 12 power steps each.  The shift starts at
+// alpha = (reg_base (||C|| + |z_dag|))^2 (at least 1e-8 (||C|| + |z_dag|)^2)
+// and is multiplied by 4 for a site whose factorization met a non-positive
+// pivot, up to 16 times.
 std::vector<int> Engine::build_sparse_sites(const std::vector<zd>& sites, const std::vector<int>& slots)
 {
     std::vector<int> ok;
@@ -133,14 +167,36 @@ std::vector<int> Engine::build_sparse_sites(const std::vector<zd>& sites, const 
     std::vector<zd> hz((size_t)NS, zmake(0.0, 0.0));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(hz.data(), d_slotz.p, sizeof(zd) * NS, hipMemcpyDeviceToHost));
-    for (int i = 0; i < ns; ++i) hz[slots[i]] = sites[i];
+    for (int i = 0; i < ns; ++i) {
+        hz[slots[i]] = sites[i];
+        const double sc = op.normC + sqrt(zabs2(sites[i]));
+        slot_alpha[slots[i]] = std::max(P.reg_base * P.reg_base, 1e-8) * sc * sc;
+    }
     h2d(d_slotz.p, hz.data(), sizeof(zd) * NS);
+    std::vector<int> todo(slots);
+    std::vector<int> bad((size_t)NS, 0);
+    for (int attempt = 0; !todo.empty(); ++attempt) {
+        if (attempt > 16) throw DeviceError("incomplete Cholesky: no positive factorization after raising the shift");
+        h2d(d_alpha.p, slot_alpha.data(), sizeof(double) * NS);
+        std::vector<int> zero((size_t)NS, 0);
+        h2d(d_icbad.p, zero.data(), sizeof(int) * NS);
+        upload_list(todo, d_listB);
+        launch_icn(d_listB.p, (int)todo.size(), sp, op.v.p, d_slotz.p, d_alpha.p, Slu.p, d_icbad.p, st);
+        HIPCHK(hipMemcpyAsync(bad.data(), d_icbad.p, sizeof(int) * NS, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<int> again;
+        for (int s : todo)
+            if (bad[s]) {
+                slot_alpha[s] *= 4.0;
+                again.push_back(s);
+                stats.ic_retries++;
+            }
+        todo.swap(again);
+    }
     upload_list(slots, d_listB);
     const int* dl = d_listB.p;
-    HIPCHK(hipMemsetAsync(d_nfloor.p, 0, sizeof(int), st));
-    launch_ilu(dl, ns, sp, op.v.p, d_slotz.p, Slu.p, d_nfloor.p, st);
-    // power iterations on (F P)^{-1} (F P)^{-*} (gamma^2) and on
-    // Tbar(z_dag) = (F P)^{-*} N(z_dag) (F P)^{-1} (lambda_n^dagger)
+    // power iterations on F^{-1} F^{-*} (gamma^2) and on
+    // Tbar(z_dag) = F^{-*} N(z_dag) F^{-1} (lambda_n^dagger)
     const int64_t sv = 4 * n, sw = (int64_t)n * KB;
     const int r3 = 3 * r;
     std::vector<double> g2(ns, 0.0), ln(ns, 0.0);
@@ -148,13 +204,13 @@ std::vector<int> Engine::build_sparse_sites(const std::vector<zd>& sites, const 
         launch_randfill(dl, ns, Svec.p, sv, n, n, 1, nullptr, 0x5ca1ull + pass, st);
         for (int it = 0; it < 12; ++it) {
             if (pass == 0) {
-                launch_ilu_solve(dl, ns, nullptr, sp, Slu.p, 1, Svec.p, sv, n, Svec.p + n, sv, n, 1, pS.p, sw, st);
-                launch_ilu_solve(dl, ns, nullptr, sp, Slu.p, 0, Svec.p + n, sv, n, Svec.p, sv, n, 1, pS.p, sw, st);
+                launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 1, Svec.p, sv, n, Svec.p + n, sv, n, 1, pS.p, sw, st);
+                launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 0, Svec.p + n, sv, n, Svec.p, sv, n, 1, pS.p, sw, st);
             } else {
-                launch_ilu_solve(dl, ns, nullptr, sp, Slu.p, 0, Svec.p, sv, n, Svec.p + n, sv, n, 1, pS.p, sw, st);
+                launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 0, Svec.p, sv, n, Svec.p + n, sv, n, 1, pS.p, sw, st);
                 apply(false, dl, ns, Svec.p + n, sv, n, Svec.p + 2 * n, sv, n, 1, d_slotz.p);
                 apply(true, dl, ns, Svec.p + 2 * n, sv, n, Svec.p + 3 * n, sv, n, 1, d_slotz.p);
-                launch_ilu_solve(dl, ns, nullptr, sp, Slu.p, 1, Svec.p + 3 * n, sv, n, Svec.p, sv, n, 1, pS.p, sw, st);
+                launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 1, Svec.p + 3 * n, sv, n, Svec.p, sv, n, 1, pS.p, sw, st);
             }
             BlockList Lp = bl_empty(n);
             bl_add(Lp, Svec.p, sv, n, 1, nullptr, 0);
@@ -171,9 +227,6 @@ std::vector<int> Engine::build_sparse_sites(const std::vector<zd>& sites, const 
             launch_scale_cols(dl, ns, Svec.p, sv, n, n, 1, nrm2.p, r3, 2, st);
         }
     }
-    int nf = 0;
-    HIPCHK(hipMemcpy(&nf, d_nfloor.p, sizeof(int), hipMemcpyDeviceToHost));
-    ilu_floors += nf;
     for (int i = 0; i < ns; ++i) {
         const int s = slots[i];
         slot_gam[s] = sqrt(std::max(g2[i], 0.0));

@@ -169,7 +169,7 @@ void Engine::finv_apply(const std::vector<int>& L, int trans, const zd* X, int64
         upload_list(L, d_listC);
         stats.sv_F += (int64_t)L.size() * r;
         const int pi = prof.begin(st, 1, 0.0, 16.0 * 2.0 * op.spat.nnz * L.size());
-        launch_ilu_solve(d_listC.p, (int)L.size(), d_tslot.p, op.spat, Slu.p, trans, X, xs, ldx, Y, ys, ldy, r, Tq.p,
+        launch_ic_solve(d_listC.p, (int)L.size(), d_tslot.p, op.spat, Slu.p, trans, X, xs, ldx, Y, ys, ldy, r, Tq.p,
                          (int64_t)n * r, st);
         prof.end(st, pi);
         return;
@@ -271,7 +271,7 @@ void Engine::proj_refresh(const std::vector<int>& slots)
             if (op.kind == PS_DENSE)
                 zgemm(dl, ns, n, KB, n, Finv.p, n, nn, trans, X, ldx, xs, Y, n, snk, 1.0, 0.0, 0, trans ? 2 : 1);
             else
-                launch_ilu_solve(dl, ns, nullptr, op.spat, Slu.p, trans, X, xs, ldx, Y, snk, n, KB, pS.p, snk, st);
+                launch_ic_solve(dl, ns, nullptr, op.spat, Slu.p, trans, X, xs, ldx, Y, snk, n, KB, pS.p, snk, st);
         };
         // pE = F^{-1} Vbar
         fsol(0, pV.p, snk, n, pE.p);

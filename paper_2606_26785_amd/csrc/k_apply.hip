@@ -210,18 +210,25 @@ void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s)
 // computed (Hermitian rank-k updates).  The K loop of a workgroup finishes
 // before its epilogue writes, so C may alias B when M <= 64 (in-place
 // left-multiplication of a panel by a small matrix).
+// TBN = 32: four waves, each 16 rows x 32 columns of the 64 x 32 tile
+// (2 MFMA blocks); TBN = 64: a 2 x 2 wave grid, each 32 x 32 of the 64 x 64
+// tile (2 x 2 MFMA blocks, half the LDS reads and global bytes per flop).
+template <int TBN, int TBK>
 __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
 {
-    __shared__ zd As[BK][BM + 1];
-    __shared__ zd Bs[BK][BN + 1];
+    constexpr int RB = (TBN == 32) ? 1 : 2;   // 16-row blocks per wave
+    __shared__ zd As[TBK][BM + 1];
+    __shared__ zd Bs[TBK][TBN + 1];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int wr0 = (TBN == 32) ? wave * 16 : (wave & 1) * 32;   // wave's first row in the tile
+    const int wc0 = (TBN == 32) ? 0 : (wave >> 1) * 32;          // wave's first column
     const int64_t i0 = (int64_t)blockIdx.x * BM;
-    const int64_t j0 = (int64_t)blockIdx.y * BN;
+    const int64_t j0 = (int64_t)blockIdx.y * TBN;
     const int nb = gridDim.z / a.splitk;
     const int bidx = blockIdx.z % nb, split = blockIdx.z / nb;
     const int tile = a.list ? a.list[bidx] : bidx;
-    if (a.upper && i0 > j0 + BN - 1) return;
+    if (a.upper && i0 > j0 + TBN - 1) return;
     const int64_t Nb = a.gtile ? (int64_t)a.gcnt[bidx] * a.cw : a.N;
     if (j0 >= Nb) return;
     const int* gt = a.gtile ? a.gtile + a.goff[bidx] : nullptr;
@@ -230,32 +237,36 @@ __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
     int64_t kend = (kbeg + kc < a.K) ? kbeg + kc : a.K;
     // triangular A: rows i0..i0+63 have nonzeros only in k >= i0 (upper) or
     // k < i0 + 64 (lower); the staging masks below keep the rest at zero
-    if (a.tri == 1 && kbeg < i0) kbeg = (i0 / BK) * BK > kbeg ? (i0 / BK) * BK : kbeg;
+    if (a.tri == 1 && kbeg < i0) kbeg = (i0 / TBK) * TBK > kbeg ? (i0 / TBK) * TBK : kbeg;
     if (a.tri == 2 && kend > i0 + BM) kend = i0 + BM;
     const zd* A = a.A + (size_t)tile * a.strideA;
     const zd* B = a.B + (size_t)(gt ? 0 : tile) * a.strideB;
     zd* C = a.C + (size_t)(gt ? 0 : tile) * a.strideC;
-    // B staging: thread tid loads rows k0 + tid % BK of columns
-    // j0 + tid / BK + (NT / BK) q, q = 0 .. BN*BK/NT - 1; their base pointers
-    // (column-map mode: through the tile map) are fixed for the whole K loop
-    constexpr int BQ = BN * BK / NT;
+    // B staging: thread tid loads rows k0 + tid % TBK of columns
+    // j0 + tid / TBK + (NT / TBK) q, q = 0 .. TBN*TBK/NT - 1; their base
+    // pointers (column-map mode: through the tile map) are fixed for the
+    // whole K loop
+    constexpr int BQ = TBN * TBK / NT;
     const zd* bcol[BQ];
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
-        int64_t gj = j0 + tid / BK + (NT / BK) * q;
+        int64_t gj = j0 + tid / TBK + (NT / TBK) * q;
         bcol[q] = nullptr;
         if (gj < Nb) bcol[q] = gt ? B + (size_t)gt[gj / a.cw] * a.strideB + (gj % a.cw) * a.ldb : B + gj * a.ldb;
     }
-    dvec4 acc_re[2], acc_im[2];
-    for (int c = 0; c < 2; ++c) {
-        acc_re[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
-        acc_im[c] = (dvec4){0.0, 0.0, 0.0, 0.0};
-    }
+    dvec4 acc_re[RB][2], acc_im[RB][2];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            acc_re[rb][c] = (dvec4){0.0, 0.0, 0.0, 0.0};
+            acc_im[rb][c] = (dvec4){0.0, 0.0, 0.0, 0.0};
+        }
     const int mrow = lane & 15, kq = lane >> 4;
     // software pipeline: the next K tile is loaded into registers while the
     // matrix cores work on the current one from LDS
-    constexpr int AQ = BM * BK / NT;
-    zd ra[AQ], rb[BQ];
+    constexpr int AQ = BM * TBK / NT;
+    zd ra[AQ], rb_[BQ];
     auto gload = [&](int64_t kt) {
         if (a.opA == 0) {
             const int64_t gi = i0 + tid % BM;
@@ -265,73 +276,86 @@ __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
                 ra[q] = (gi < a.M && gk < kend) ? A[gi + gk * a.lda] : zmake(0.0, 0.0);
             }
         } else {
-            const int64_t gk = kt + tid % BK;
+            const int64_t gk = kt + tid % TBK;
 #pragma unroll
             for (int q = 0; q < AQ; ++q) {
-                const int64_t gi = i0 + tid / BK + (NT / BK) * q;
+                const int64_t gi = i0 + tid / TBK + (NT / TBK) * q;
                 ra[q] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
             }
         }
 #pragma unroll
         for (int q = 0; q < BQ; ++q) {
-            const int64_t gk = kt + tid % BK;
-            rb[q] = (bcol[q] && gk < kend) ? bcol[q][gk] : zmake(0.0, 0.0);
+            const int64_t gk = kt + tid % TBK;
+            rb_[q] = (bcol[q] && gk < kend) ? bcol[q][gk] : zmake(0.0, 0.0);
         }
     };
     if (kbeg < kend) gload(kbeg);
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    for (int64_t k0 = kbeg; k0 < kend; k0 += TBK) {
         if (a.opA == 0) {
 #pragma unroll
             for (int q = 0; q < AQ; ++q) As[tid / BM + (NT / BM) * q][tid % BM] = ra[q];
         } else {
 #pragma unroll
-            for (int q = 0; q < AQ; ++q) As[tid % BK][tid / BK + (NT / BK) * q] = ra[q];
+            for (int q = 0; q < AQ; ++q) As[tid % TBK][tid / TBK + (NT / TBK) * q] = ra[q];
         }
 #pragma unroll
-        for (int q = 0; q < BQ; ++q) Bs[tid % BK][tid / BK + (NT / BK) * q] = rb[q];
+        for (int q = 0; q < BQ; ++q) Bs[tid % TBK][tid / TBK + (NT / TBK) * q] = rb_[q];
         __syncthreads();
-        if (k0 + BK < kend) gload(k0 + BK);
+        if (k0 + TBK < kend) gload(k0 + TBK);
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            zd av = As[ks + kq][wave * 16 + mrow];
-            double ar = av.x, ai = av.y, nai = -av.y;
+        for (int ks = 0; ks < TBK; ks += 4) {
+            double ar[RB], ai[RB], nai[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const zd av = As[ks + kq][wr0 + rb * 16 + mrow];
+                ar[rb] = av.x;
+                ai[rb] = av.y;
+                nai[rb] = -av.y;
+            }
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                zd xv = Bs[ks + kq][cb * 16 + mrow];
-                acc_re[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xv.x, acc_re[cb], 0, 0, 0);
-                acc_re[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, xv.y, acc_re[cb], 0, 0, 0);
-                acc_im[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xv.y, acc_im[cb], 0, 0, 0);
-                acc_im[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xv.x, acc_im[cb], 0, 0, 0);
+                const zd xv = Bs[ks + kq][wc0 + cb * 16 + mrow];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    acc_re[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[rb], xv.x, acc_re[rb][cb], 0, 0, 0);
+                    acc_re[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[rb], xv.y, acc_re[rb][cb], 0, 0, 0);
+                    acc_im[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[rb], xv.y, acc_im[rb][cb], 0, 0, 0);
+                    acc_im[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[rb], xv.x, acc_im[rb][cb], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
     }
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
-        int64_t col = j0 + cb * 16 + (lane & 15);
+        int64_t col = j0 + wc0 + cb * 16 + (lane & 15);
         if (col >= Nb) continue;
         zd* ccol = gt ? C + (size_t)gt[col / a.cw] * a.strideC + (col % a.cw) * a.ldc : C + col * a.ldc;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            int64_t row = i0 + wave * 16 + (lane >> 4) + 4 * v;
-            if (row >= a.M) continue;
-            if (a.splitk > 1) {
-                a.ws[((size_t)split * nb + bidx) * a.M * a.N + row + (size_t)col * a.M] =
-                    zmake(acc_re[cb][v], acc_im[cb][v]);
-                continue;
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t row = i0 + wr0 + rb * 16 + (lane >> 4) + 4 * v;
+                if (row >= a.M) continue;
+                if (a.splitk > 1) {
+                    a.ws[((size_t)split * nb + bidx) * a.M * a.N + row + (size_t)col * a.M] =
+                        zmake(acc_re[rb][cb][v], acc_im[rb][cb][v]);
+                    continue;
+                }
+                zd val = zmake(a.alpha * acc_re[rb][cb][v], a.alpha * acc_im[rb][cb][v]);
+                zd* cp = ccol + row;
+                if (a.beta != 0.0) val = zadd(val, *cp);
+                *cp = val;
             }
-            zd val = zmake(a.alpha * acc_re[cb][v], a.alpha * acc_im[cb][v]);
-            zd* cp = ccol + row;
-            if (a.beta != 0.0) val = zadd(val, *cp);
-            *cp = val;
-        }
     }
 }
 
-// two names for one kernel (k_zgemm: preconditioner applies; k_zgemm_fact:
-// products inside factorizations), so that profiles separate them
-__global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a) { k_zgemm_body(a); }
-__global__ void __launch_bounds__(NT) k_zgemm_fact(ZgemmArgs a) { k_zgemm_body(a); }
+// k_zgemm: preconditioner applies and small products; k_zgemm_fact and
+// k_zgemm_fact64: products inside factorizations (64 x 32 and 64 x 64
+// tiles), under their own names so that profiles separate them
+__global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a) { k_zgemm_body<32, BK>(a); }
+__global__ void __launch_bounds__(NT) k_zgemm_fact(ZgemmArgs a) { k_zgemm_body<32, BK>(a); }
+__global__ void __launch_bounds__(NT) k_zgemm_fact64(ZgemmArgs a) { k_zgemm_body<64, 16>(a); }
 
 // sum of the split-K partials into C (alpha, beta as in k_zgemm)
 __global__ void __launch_bounds__(NT) k_zgemm_reduce(ZgemmArgs a, int nb)
@@ -360,139 +384,15 @@ void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact)
 {
     if (nbatch <= 0 || a.M <= 0 || a.N <= 0) return;
     const int sk = a.splitk > 1 ? a.splitk : 1;
-    dim3 g((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + BN - 1) / BN), nbatch * sk);
-    if (fact) hipLaunchKernelGGL(k_zgemm_fact, g, dim3(NT), 0, s, a);
+    // factorization products at least 64 columns wide: 64 x 64 tiles
+    const bool t64 = (fact == 2) && !a.gtile && a.N >= 64;
+    const int tbn = t64 ? 64 : BN;
+    dim3 g((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + tbn - 1) / tbn), nbatch * sk);
+    if (t64) hipLaunchKernelGGL(k_zgemm_fact64, g, dim3(NT), 0, s, a);
+    else if (fact) hipLaunchKernelGGL(k_zgemm_fact, g, dim3(NT), 0, s, a);
     else hipLaunchKernelGGL(k_zgemm, g, dim3(NT), 0, s, a);
     if (sk > 1) {
         dim3 g2((unsigned)((a.M * a.N + NT - 1) / NT), nbatch);
         hipLaunchKernelGGL(k_zgemm_reduce, g2, dim3(NT), 0, s, a, nbatch);
     }
-}
-
-// ---------------------------------------------------------------------------
-// Wide-tile batched complex GEMM for the factorisations (trailing Hermitian
-// updates and the large products that form F^{-1}):
-//   C_b = alpha op(A_b) B_b + beta C_b, op(A) = A or A^*,
-// 128 x 64 output tiles per workgroup, each of the four waves owning a
-// 64 x 32 quadrant (4 x 2 blocks of 16 x 16, re/im accumulators), K staged
-// 16 at a time through LDS with the next K tile loaded into registers while
-// the matrix cores work.  Per 4-deep K step a wave reads 6 complex operand
-// fragments from LDS for 32 v_mfma_f64_16x16x4f64 (the 64 x 32 kernel above:
-// 3 for 8), and a K tile of 128 + 64 rows carries 16 x 128 x 64 complex
-// multiply-adds (twice the flop per byte of the 64 x 32 tile).  upper: only
-// tiles touching the upper triangle of C; tri: A upper (1) or lower (2)
-// triangular, zero K ranges skipped.
-#define WBM 128
-#define WBN 64
-#define WBK 16
-__global__ void __launch_bounds__(NT) k_zgemm_wide(ZgemmArgs a)
-{
-    __shared__ zd As[WBK][WBM + 1];
-    __shared__ zd Bs[WBK][WBN + 1];
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int64_t i0 = (int64_t)blockIdx.x * WBM;
-    const int64_t j0 = (int64_t)blockIdx.y * WBN;
-    const int tile = a.list ? a.list[blockIdx.z] : blockIdx.z;
-    if (a.upper && i0 > j0 + WBN - 1) return;
-    if (j0 >= a.N) return;
-    int64_t kbeg = 0, kend = a.K;
-    if (a.tri == 1 && kbeg < i0) kbeg = (i0 / WBK) * WBK;
-    if (a.tri == 2 && kend > i0 + WBM) kend = i0 + WBM;
-    const zd* A = a.A + (size_t)tile * a.strideA;
-    const zd* B = a.B + (size_t)tile * a.strideB;
-    zd* C = a.C + (size_t)tile * a.strideC;
-    dvec4 acc_re[8], acc_im[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        acc_re[q] = (dvec4){0.0, 0.0, 0.0, 0.0};
-        acc_im[q] = (dvec4){0.0, 0.0, 0.0, 0.0};
-    }
-    const int mrow = lane & 15, kq = lane >> 4;
-    constexpr int AQ = WBM * WBK / NT, BQ = WBN * WBK / NT;   // 8, 4
-    zd ra[AQ], rb[BQ];
-    auto gload = [&](int64_t kt) {
-        if (a.opA == 0) {
-            const int64_t gi = i0 + tid % WBM;
-#pragma unroll
-            for (int q = 0; q < AQ; ++q) {
-                const int64_t gk = kt + tid / WBM + (NT / WBM) * q;
-                ra[q] = (gi < a.M && gk < kend) ? A[gi + gk * a.lda] : zmake(0.0, 0.0);
-            }
-        } else {
-            const int64_t gk = kt + tid % WBK;
-#pragma unroll
-            for (int q = 0; q < AQ; ++q) {
-                const int64_t gi = i0 + tid / WBK + (NT / WBK) * q;
-                ra[q] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
-            }
-        }
-        const int64_t gk = kt + tid % WBK;
-#pragma unroll
-        for (int q = 0; q < BQ; ++q) {
-            const int64_t gj = j0 + tid / WBK + (NT / WBK) * q;
-            rb[q] = (gj < a.N && gk < kend) ? B[gk + gj * a.ldb] : zmake(0.0, 0.0);
-        }
-    };
-    if (kbeg < kend) gload(kbeg);
-    for (int64_t k0 = kbeg; k0 < kend; k0 += WBK) {
-        if (a.opA == 0) {
-#pragma unroll
-            for (int q = 0; q < AQ; ++q) As[tid / WBM + (NT / WBM) * q][tid % WBM] = ra[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < AQ; ++q) As[tid % WBK][tid / WBK + (NT / WBK) * q] = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < BQ; ++q) Bs[tid % WBK][tid / WBK + (NT / WBK) * q] = rb[q];
-        __syncthreads();
-        if (k0 + WBK < kend) gload(k0 + WBK);
-#pragma unroll
-        for (int ks = 0; ks < WBK; ks += 4) {
-            zd av[4], bv[2];
-#pragma unroll
-            for (int r4 = 0; r4 < 4; ++r4) av[r4] = As[ks + kq][wr * 64 + r4 * 16 + mrow];
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) bv[c2] = Bs[ks + kq][wc * 32 + c2 * 16 + mrow];
-#pragma unroll
-            for (int r4 = 0; r4 < 4; ++r4) {
-                const double ar = av[r4].x, ai = av[r4].y, nai = -av[r4].y;
-#pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2) {
-                    const int q = r4 * 2 + c2;
-                    acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv[c2].x, acc_re[q], 0, 0, 0);
-                    acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bv[c2].y, acc_re[q], 0, 0, 0);
-                    acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bv[c2].y, acc_im[q], 0, 0, 0);
-                    acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bv[c2].x, acc_im[q], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // D layout: lane l, element v -> row (l / 16) + 4 v, column l % 16 of a 16 x 16 block
-#pragma unroll
-    for (int r4 = 0; r4 < 4; ++r4)
-#pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) {
-            const int q = r4 * 2 + c2;
-            const int64_t col = j0 + wc * 32 + c2 * 16 + (lane & 15);
-            if (col >= a.N) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = i0 + wr * 64 + r4 * 16 + (lane >> 4) + 4 * v;
-                if (row >= a.M) continue;
-                zd val = zmake(a.alpha * acc_re[q][v], a.alpha * acc_im[q][v]);
-                zd* cp = C + row + col * a.ldc;
-                if (a.beta != 0.0) val = zadd(val, *cp);
-                *cp = val;
-            }
-        }
-}
-
-void launch_zgemm_wide(const ZgemmArgs& a, int nbatch, hipStream_t s)
-{
-    if (nbatch <= 0 || a.M <= 0 || a.N <= 0) return;
-    dim3 g((unsigned)((a.M + WBM - 1) / WBM), (unsigned)((a.N + WBN - 1) / WBN), nbatch);
-    hipLaunchKernelGGL(k_zgemm_wide, g, dim3(NT), 0, s, a);
 }

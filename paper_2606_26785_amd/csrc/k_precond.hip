@@ -40,12 +40,11 @@ void launch_form_normal(const int* list, int nt, const zd* CtC, const zd* C, int
 // (chunk, matrix) factors the diagonal block A_kk (kb <= 32, upper triangle
 // read) redundantly in LDS and forms X = R_kk^{-1}; chunk 0 writes X into
 // Dinv and into the diagonal block of Finv (when non-null) and raises notpd
-// on a non-positive pivot; chunk c >= 1 turns columns
-// k1 + (c - 1) PANEL_CHUNK ... of the block row (PANEL_W at a time) into the
-// row panel of the factor,
-// A[k, cols] <- X^* A[k, cols] (= R_kk^{-*} A[k, cols]).  Replaces a
-// single-workgroup diagonal kernel plus a separate panel product per step.
-#define PANEL_W 64
+// on a non-positive pivot; chunk c >= 1 turns the PANEL_CHUNK columns
+// k1 + (c - 1) PANEL_CHUNK ... of the block row (one per thread) into the
+// row panel of the factor, A[k, cols] <- R_kk^{-*} A[k, cols] by forward
+// substitution.  Replaces a single-workgroup diagonal kernel plus a
+// separate panel product per step.
 #define PANEL_CHUNK 256
 __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_t strideA, int64_t n, int64_t k0,
                                                   int kb, zd* Dinv, int64_t strideD, zd* Finv, int64_t strideF,
@@ -53,7 +52,6 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
 {
     __shared__ zd R[32][33];
     __shared__ zd X[32][33];
-    __shared__ zd Pn[32][PANEL_W + 1];
     __shared__ int bad;
     const int tile = list[blockIdx.y];
     const int chunk = blockIdx.x;
@@ -115,30 +113,26 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
         }
         return;
     }
-    const int64_t cend = (cbeg + PANEL_CHUNK < n) ? cbeg + PANEL_CHUNK : n;
-    for (int64_t c0 = cbeg; c0 < cend; c0 += PANEL_W) {
-        const int w = (int)((cend - c0) < PANEL_W ? (cend - c0) : PANEL_W);
-        for (int e = tid; e < kb * PANEL_W; e += NT) {
-            int i = e % kb, c = e / kb;
-            Pn[i][c] = (c < w) ? Ab[k0 + i + (c0 + c) * n] : zmake(0.0, 0.0);
+    // R_kk^* Y = A[k, c] for the columns c of this chunk: one column per
+    // thread, held in registers, forward substitution with R read from LDS
+    const int64_t c = cbeg + tid;
+    if (c >= n) return;
+    zd* col = Ab + k0 + c * n;
+    zd y[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) y[i] = (i < kb) ? col[i] : zmake(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        if (i < kb) {
+            zd sacc = y[i];
+#pragma unroll
+            for (int l = 0; l < i; ++l) sacc = zsub(sacc, zcmul(R[l][i], y[l]));
+            y[i] = zscale(sacc, 1.0 / R[i][i].x);
         }
-        __syncthreads();
-        // R_kk^* Y = A[k, cols]: forward substitution, one thread per column
-        if (tid < w) {
-            const int c = tid;
-            for (int i = 0; i < kb; ++i) {
-                zd sacc = Pn[i][c];
-                for (int l = 0; l < i; ++l) sacc = zsub(sacc, zcmul(R[l][i], Pn[l][c]));
-                Pn[i][c] = zscale(sacc, 1.0 / R[i][i].x);
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < kb * w; e += NT) {
-            int i = e % kb, c = e / kb;
-            Ab[k0 + i + (c0 + c) * n] = Pn[i][c];
-        }
-        __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        if (i < kb) col[i] = y[i];
 }
 
 void launch_chol_step(const int* list, int nt, zd* A, int64_t strideA, int64_t n, int64_t k0, int kb, zd* Dinv,

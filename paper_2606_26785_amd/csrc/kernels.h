@@ -191,8 +191,6 @@ struct ZgemmArgs {
     const int* gtile; const int* goff; const int* gcnt; int cw;
 };
 void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact = 0);
-// 128 x 64 tiles, no column map, no split K (large factorisation products)
-void launch_zgemm_wide(const ZgemmArgs& a, int nbatch, hipStream_t s);
 
 // dense base preconditioner (k_precond.hip)
 #define PRE_NB 32
@@ -211,13 +209,19 @@ struct SparsePattern {
     int ncolors = 0;
     const int64_t* cptr = nullptr;                  // host array, ncolors + 1
     const int64_t* rp = nullptr; const int32_t* ci = nullptr;
-    const int64_t* src = nullptr;                   // entry -> entry of C's CSR, -1 for an added diagonal
+    // contributions of each entry e of N = C(z)^* C(z): pairs (ca[q], cb[q]),
+    // q in [ccp[e], ccp[e + 1]), naming entries of C - z I (see k_sparse.hip)
+    const int64_t* ccp = nullptr; const int64_t* ca = nullptr; const int64_t* cb = nullptr;
     const int64_t* diag = nullptr;                  // row -> its diagonal entry
     const int64_t* rpT = nullptr; const int32_t* ciT = nullptr; const int64_t* mapT = nullptr;  // transpose
     const int* perm = nullptr;                      // permuted row -> original row
 };
-void launch_ilu(const int* list, int ns, const SparsePattern& sp, const zd* vC, const zd* zsite, zd* lu, int* nfloor,
-                hipStream_t s);
-void launch_ilu_solve(const int* list, int ni, const int* site, const SparsePattern& sp, const zd* lu, int trans,
-                      const zd* X, int64_t xs, int64_t ldx, zd* Y, int64_t ys, int64_t ldy, int w, zd* T, int64_t ts,
-                      hipStream_t s);
+// incomplete Cholesky factors of N(z_site) + alpha_site I for the listed
+// sites (notpd[site] set on a non-positive pivot)
+void launch_icn(const int* list, int ns, const SparsePattern& sp, const zd* vC, const zd* zsite, const double* alpha,
+                zd* lu, int* notpd, hipStream_t s);
+// Y = F^{-1} X (trans 0) or F^{-*} X (trans 1), K = F^* F the incomplete
+// Cholesky factorization of each item's site
+void launch_ic_solve(const int* list, int ni, const int* site, const SparsePattern& sp, const zd* lu, int trans,
+                     const zd* X, int64_t xs, int64_t ldx, zd* Y, int64_t ys, int64_t ldy, int w, zd* T, int64_t ts,
+                     hipStream_t s);

@@ -98,6 +98,7 @@ void ps_default_params(ps_params* p)
     p->cert_recycled = 0;
     p->lipschitz = 1;
     p->reg_base = 0.02;
+    p->fact_blas = 0;
 }
 
 const char* ps_strerror(ps_status s)
@@ -138,6 +139,7 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
         return fail(PS_EINVAL, "kbar_max must be a multiple of rbar, <= 64");
     if (p.max_iters < 1 || p.batch < 1) return fail(PS_EINVAL, "max_iters and batch must be positive");
     if (p.traversal < 0 || p.traversal > 2) return fail(PS_EINVAL, "traversal must be 0, 1 or 2");
+    if (p.fact_blas < 0 || p.fact_blas > 1) return fail(PS_EINVAL, "fact_blas must be 0 or 1");
     if (p.tile_points < 1 || p.tile_mem_gb < 1 || p.site_mem_gb < 1)
         return fail(PS_EINVAL, "tile_points, tile_mem_gb and site_mem_gb must be positive");
     if (!(p.eta > 0) || !(p.eta_svd > 0) || !(p.omega >= 1.0) || !(p.eta_abs >= 0) || p.eta_abs > 1e-8 ||
@@ -407,6 +409,43 @@ extern "C" ps_status ps_debug_site(ps_matrix* h, double* dreg, double* gamma)
             return PS_OK;
         }
     return fail(PS_EINVAL, "no site built");
+}
+
+// One sparse base site at z: Y = F^{-1} X (trans 0) or F^{-*} X (trans 1).
+extern "C" ps_status ps_debug_sparse_site(ps_matrix* h, double z_re, double z_im, int32_t trans, const double* X,
+                                          int32_t w, double* Y, double* alpha)
+{
+    if (!h || !X || !Y || !alpha) return fail(PS_EINVAL, "NULL argument");
+    if (w < 1 || w > 64 || trans < 0 || trans > 1) return fail(PS_EINVAL, "w must be 1..64, trans 0 or 1");
+    try {
+        Engine& E = h->eng;
+        if (E.op.kind == PS_DENSE || !E.use_prec) return fail(PS_EUNSUPPORTED, "no sparse base preconditioner");
+        if (E.T < 1 || E.NS < 1) E.size_for(std::max(E.T, 1));
+        E.reset_slots();
+        std::vector<int> sl = E.build_precond({zmake(z_re, z_im)});
+        if (sl.empty() || sl[0] < 0) return fail(PS_ENOMEM, "no preconditioner slot");
+        const int64_t n = E.n;
+        DBuf<zd> dX, dY, dT;
+        DBuf<int> dl, ds;
+        dX.alloc((size_t)n * w);
+        dY.alloc((size_t)n * w);
+        dT.alloc((size_t)n * w);
+        dl.alloc(1);
+        ds.alloc(1);
+        const int zero = 0;
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(dl.p, &zero, sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ds.p, &sl[0], sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dX.p, X, sizeof(zd) * n * w, hipMemcpyHostToDevice));
+        launch_ic_solve(dl.p, 1, ds.p, E.op.spat, E.Slu.p, trans, dX.p, 0, n, dY.p, 0, n, w, dT.p, 0, E.st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(E.st));
+        HIPCHK(hipMemcpy(Y, dY.p, sizeof(zd) * n * w, hipMemcpyDeviceToHost));
+        *alpha = E.slot_alpha[sl[0]];
+        return PS_OK;
+    } catch (const std::exception& e) {
+        return fail(PS_EDEVICE, e.what());
+    }
 }
 
 // The recycled singular store of one tile as the last ps_eval left it.

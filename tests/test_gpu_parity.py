@@ -204,12 +204,15 @@ def test_folding_rectangular_parity():
     _check_parity(wl, res, ref, nC, "folding n=200 m=204 10x10")
 
 
+@pytest.mark.parametrize("fact_blas", [1, 0])
 @pytest.mark.parametrize("n,m", [(100, 100), (300, 300), (257, 261), (1100, 1100)])
-def test_dense_base_preconditioner(n, m):
-    """F^{-1} from the blocked Cholesky: F^{-*} (N(z) + delta I) F^{-1} = I."""
+def test_dense_base_preconditioner(n, m, fact_blas):
+    """F^{-1} from the blocked Cholesky: F^{-*} (N(z) + delta I) F^{-1} = I,
+    with the factorization's plain products on rocBLAS (1) or on the
+    library's own matrix-core kernel (0)."""
     rng = np.random.default_rng(n)
     C = _cplx(rng, m, n)
-    mat = P.ps_create(dense=C, params=P.default_params(precond=1))
+    mat = P.ps_create(dense=C, params=P.default_params(precond=1, fact_blas=fact_blas))
     z = 0.4 - 0.25j
     Finv, gamma = P.debug_precond(mat, z)
     A = C.copy()

@@ -1,5 +1,5 @@
 """The sparse path on the GPU (marked gpu): a CSR convection-diffusion C with
-the two-level preconditioner over an incomplete-LU base (paper Sec. 3),
+the two-level preconditioner over an incomplete-Cholesky base (paper Sec. 3),
 against the oracle.
 
 * reduced instances (N = 30 and N = 50, n = 900 and 2,500) on whole grids,
@@ -63,6 +63,36 @@ def test_convdiff_reduced_parity(N, grid, ref_kind):
     res = _eval(wl, wl.region, wl.nx, wl.ny)
     _check(res, ref, normC, wl.eps, "convdiff N=%d %dx%d" % (N, grid, grid))
     assert res.stats["rebuilds"] >= 1
+
+
+@pytest.mark.parametrize("N,which", [(12, "centre"), (17, "corner")])
+def test_incomplete_cholesky_site(N, which):
+    """The sparse base site: K = F^* F from the GPU factor agrees with
+    N(z) + alpha I on the pattern of C^* C (incomplete Cholesky without fill
+    is exact there), K is Hermitian positive definite, and F^{-*} is the
+    conjugate transpose of F^{-1}."""
+    wl = workloads.convection_diffusion(N=N, grid=4)
+    n = wl.n
+    z = wl.z_center if which == "centre" else complex(wl.region[0], wl.region[2])
+    mat = P.create_from_workload(wl, params=P.default_params(precond=1))
+    try:
+        I = np.eye(n, dtype=np.complex128)
+        Fi = np.hstack([P.debug_sparse_site(mat, z, I[:, c:c + 64], 0)[0] for c in range(0, n, 64)])
+        Fh = np.hstack([P.debug_sparse_site(mat, z, I[:, c:c + 64], 1)[0] for c in range(0, n, 64)])
+        alpha = P.debug_sparse_site(mat, z, I[:, :1], 0)[1]
+    finally:
+        mat.close()
+    assert alpha > 0
+    assert np.max(np.abs(Fh - Fi.conj().T)) <= 1e-12 * np.max(np.abs(Fi))
+    F = np.linalg.inv(Fi)
+    K = F.conj().T @ F
+    A = wl.to_dense() - z * np.eye(n)
+    Nz = A.conj().T @ A + alpha * np.eye(n)
+    pat = (np.abs(wl.to_dense().conj().T) @ np.abs(wl.to_dense()) + np.eye(n)) > 0
+    scale = np.max(np.abs(Nz))
+    assert np.max(np.abs((K - Nz)[pat])) <= 1e-10 * scale
+    assert np.max(np.abs(K - K.conj().T)) <= 1e-10 * scale
+    assert np.linalg.eigvalsh(0.5 * (K + K.conj().T)).min() > 0
 
 
 def test_convdiff_base_only_parity():
