@@ -48,6 +48,35 @@ CLASS_KERNELS = ["k_dense_gemm + k_dense_reduce (dense) or k_csr_apply (CSR)", "
                  "copies, fills", "k_zgemm_fact (+ k_zgemm_reduce)"]
 
 
+def measured_traffic(kernel):
+    """The HBM traffic per launch of `kernel` stored in profiles/<kernel>_traffic.md
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by a copy of known
+    size), or None when there is none or the kernel's source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_traffic.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        line = line.strip()
+        if ":" in line and line.split(":", 1)[0] in ("kernel_source", "kernel_source_sha256",
+                                                      "traffic_bytes_per_launch", "algorithmic_bytes_per_launch",
+                                                      "workload"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    try:
+        src = open(os.path.join(ROOT, fields["kernel_source"]), "rb").read()
+    except (KeyError, OSError):
+        return None
+    if hashlib.sha256(src).hexdigest() != fields.get("kernel_source_sha256"):
+        return None
+    t = float(fields["traffic_bytes_per_launch"])
+    a = float(fields["algorithmic_bytes_per_launch"])
+    return {"bytes_per_launch": t, "over_algorithmic": t / a, "workload": fields.get("workload"),
+            "source": "profiles/%s_traffic.md" % kernel}
+
+
 def path_work(st, n, r, k):
     """Algorithmic flops and HBM bytes of one ps_eval from the library's
     counters.  Complex multiply-add = 8 real flops.
@@ -217,8 +246,10 @@ def main():
             achieved, peak, unit = by / (avg_ms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
         else:
             achieved, peak, unit = fl / (avg_ms * 1e-3) / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+        tr = measured_traffic(CLASS_KERNELS[c]) if " " not in CLASS_KERNELS[c] else None
         roofline = {"bound": CLASS_BOUND[c], "achieved": achieved, "peak": peak, "unit": unit,
-                    "frac": achieved / peak, "traffic": None, "kernel_class": CLASS_NAMES[c], "kernels": CLASS_KERNELS[c],
+                    "frac": achieved / peak, "traffic": tr["bytes_per_launch"] if tr else None,
+                    "traffic_detail": tr, "kernel_class": CLASS_NAMES[c], "kernels": CLASS_KERNELS[c],
                     "launches": int(launches), "avg_launch_ms": avg_ms, "flops_per_launch": fl,
                     "bytes_per_launch": by,
                     "device_ms_by_class": {CLASS_NAMES[i]: kms[i] for i in range(len(kms)) if kms[i] > 0},
@@ -354,7 +385,8 @@ def main():
         "stats": {k: st[k] for k in ("accepted", "refined", "uncertified", "certified", "lipschitz_redo",
                                      "lobpcg_iters", "precond_iters", "ritz_jobs", "store_updates", "rebuilds",
                                      "cert_tests", "repairs", "rounds", "mv_M", "sv_F", "proj_accepted",
-                                     "proj_refined", "proj_iters", "ic_retries", "t_ritz_ms",
+                                     "proj_refined", "proj_iters", "ic_retries", "builds_shared",
+                                     "builds_private", "t_ritz_ms",
                                      "t_lobpcg_ms", "t_update_ms", "t_precond_ms")},
         "parity": parity,
         "create_s": t_create,
