@@ -20,13 +20,13 @@
  *  - 1 (dense default): base preconditioner K = F^* F = N(z_dag) + delta I,
  *    an exact Cholesky factor at sites z_dag placed by a base-only form of
  *    the rebuild rule (eq. (tauRecycle) with the projection part empty);
- *  - 2 (square CSR default): the two-level preconditioner of eq.
+ *  - 2 (CSR default): the two-level preconditioner of eq.
  *    (twolevel): an incomplete-Cholesky base of N(z_dag) (CSR) or a
  *    regularised Cholesky base
  *    (dense), plus a projection subspace recycled by Alg. 4 (recyProj) and
  *    eq. (tolTz), refined by LOBPCG-SVD on Mbar(z) = C(z) F^{-1} when the
  *    test fails, and the full rebuild rule of eq. (tauRecycle);
- *  - 0 (rectangular CSR default): K = I.
+ *  - 0: K = I.
  * Every numerical step runs in HIP kernels on the GPU in complex128.
  *
  * Conventions
@@ -109,14 +109,13 @@ typedef struct {
                            (Alg. 4 and 5), K = F^* F with F the Cholesky
                            factor of N(z_dag) + (reg_base (||C|| + |z_dag|))^2 I,
                            rebuilt by the rule of eq. (tauRecycle);
-                           For a square CSR C, K = L D L^* is instead the
+                           For CSR C, K = L D L^* is instead the
                            incomplete Cholesky factorization (no fill, on
                            the pattern of C^* C in a colour ordering of its
                            graph) of N(z_dag) + alpha I, alpha starting at
                            (reg_base (||C|| + |z_dag|))^2 and raised 4x
                            until every pivot is positive; F = D^{1/2} L^* P.
-                           -1 (default): 1 for dense C, 2 for square CSR,
-                           0 for rectangular CSR */
+                           -1 (default): 1 for dense C, 2 for CSR */
     int32_t tiles_x;    /* grid-front partition: tiles along x (0 = auto) */
     int32_t tiles_y;    /* tiles along y (0 = auto) */
     int32_t tile_points;/* auto partition: points per tile (default 80) */
@@ -260,7 +259,6 @@ void ps_default_params(ps_params* p);
  * recycled stores.  desc is read during the call only (unless on_device).
  * hip_stream: the hipStream_t all work is issued on (NULL = default).
  * Errors: PS_EINVAL (m < n, n < 1, bad CSR, NULL pointers, bad params),
- * PS_EUNSUPPORTED (a preconditioner on a rectangular CSR matrix),
  * PS_ENOMEM, PS_EDEVICE; *out is NULL on error. */
 ps_status ps_create(const ps_matrix_desc* desc, const ps_params* params, void* hip_stream,
                     ps_matrix** out);

@@ -301,7 +301,7 @@ struct Engine {
     // ---- building blocks
     void upload_list(const std::vector<int>& L, DBuf<int>& dst);
     void gram(const int* dlist, int nt, const BlockList& A, const BlockList& Bl, int camax, int cbmax, void* out,
-              int64_t strideOut, int ldOut, bool dd, bool upper);
+              int64_t strideOut, int ldOut, bool dd, bool upper, bool out_dd = false);
     void gemm_ts(const int* dlist, int nt, const BlockList& A, int camax, const zd* G, int64_t strideG, int ldG,
                  const int* cbdims, int cbmul, int cb, zd* Y, int64_t strideY, int64_t ldY, int64_t rows,
                  double alpha, double beta);
@@ -309,8 +309,11 @@ struct Engine {
     void orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, int64_t wstride, int64_t ldw,
                         int64_t rows, int cols, const BlockList* against, int against_max, uint64_t seed);
     // nzero (optional, per tile): number of pivots the Cholesky treated as zero
+    // dd_gram: Gram matrix accumulated in double-double (mixed-precision
+    // Cholesky QR); false: in double, where its rounding is known to be small
     void r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul, int cfixed,
-                  zd* R, int64_t strideR, int ldR, int* nzero = nullptr, zdd* gbuf = nullptr);
+                  zd* R, int64_t strideR, int ldR, int* nzero = nullptr, zdd* gbuf = nullptr, bool dd_gram = true);
+    DBuf<int> d_listDD, d_listPL;   // LOBPCG tiles whose R factor uses the double-double / double Gram
 
     // ---- algorithm steps
     // LOBPCG-SVD as a per-tile state machine: lob_start runs the first

@@ -155,7 +155,7 @@ void Engine::upload_list(const std::vector<int>& L, DBuf<int>& dst)
 }
 
 void Engine::gram(const int* dlist, int nt, const BlockList& A, const BlockList& Bl, int camax, int cbmax,
-                  void* out, int64_t strideOut, int ldOut, bool dd, bool upper)
+                  void* out, int64_t strideOut, int ldOut, bool dd, bool upper, bool out_dd)
 {
     if (nt <= 0) return;
     GramArgs g;
@@ -172,6 +172,7 @@ void Engine::gram(const int* dlist, int nt, const BlockList& A, const BlockList&
     g.part = gram_ws.p;
     g.dd = dd ? 1 : 0;
     g.hermitian_upper_only = upper ? 1 : 0;
+    g.out_dd = (!dd && out_dd) ? 1 : 0;
     size_t esz = dd ? sizeof(zdd) : sizeof(zd);
     // rows per chunk: enough chunks to fill the GPU, within the workspace
     int64_t rows = A.rows;
@@ -250,11 +251,11 @@ void Engine::colnorm2(const int* dlist, int nt, const BlockList& A, int camax, d
 // double-double accuracy, so R equals the R factor of a backward-stable QR
 // of A up to rounding of R itself.
 void Engine::r_factor(const int* dlist, int nt, const BlockList& A, int cmax, const int* cdims, int cmul,
-                      int cfixed, zd* R, int64_t strideR, int ldR, int* nzero, zdd* gbuf)
+                      int cfixed, zd* R, int64_t strideR, int ldR, int* nzero, zdd* gbuf, bool dd_gram)
 {
     if (nt <= 0) return;
     zdd* gb = gbuf ? gbuf : gdd.p;
-    gram(dlist, nt, A, A, cmax, cmax, gb, (int64_t)cmax * cmax, cmax, true, true);
+    gram(dlist, nt, A, A, cmax, cmax, gb, (int64_t)cmax * cmax, cmax, dd_gram, true, true);
     CholArgs c;
     memset(&c, 0, sizeof(c));
     c.list = dlist;
@@ -303,7 +304,11 @@ void Engine::orthonormalize(const std::vector<int>& L, const int* dlist, zd* W, 
             hipLaunchKernelGGL(k_scale_cols_rsqrt, g, dim3(256), 0, st, dlist, W, wstride, ldw, rows, cols, nrm2.p,
                                3 * r);
         }
-        r_factor(dlist, nt, Wl, cols, nullptr, 0, cols, Rsm.p, (int64_t)9 * r * r, 3 * r);
+        // the Gram matrix of the unit-norm columns in double: directions
+        // below the drop level 1e-6 are refilled, and the at least two
+        // passes below bring the rest to orthonormality as Cholesky QR
+        // twice does
+        r_factor(dlist, nt, Wl, cols, nullptr, 0, cols, Rsm.p, (int64_t)9 * r * r, 3 * r, nullptr, nullptr, false);
         SvqbArgs sa;
         memset(&sa, 0, sizeof(sa));
         sa.list = dlist;
@@ -470,9 +475,7 @@ void Engine::create(const ps_matrix_desc* d, const ps_params* p, hipStream_t s)
     m = op.m;
     r = P.r;
     K = P.k_max;
-    if (P.precond < 0) P.precond = (op.kind == PS_DENSE) ? 1 : (m == n ? 2 : 0);
-    if (P.precond > 0 && op.kind != PS_DENSE && m != n)
-        throw InvalidArg("the sparse base preconditioner needs a square matrix");
+    if (P.precond < 0) P.precond = (op.kind == PS_DENSE) ? 1 : 2;
     use_prec = P.precond > 0;
     two_level = P.precond == 2;
     if (use_prec && op.kind != PS_DENSE) build_sparse_pattern();
@@ -590,10 +593,10 @@ void Engine::size_for(int tiles)
         // incomplete Cholesky sites: values, power-iteration vectors, solve work;
         // the projection stores (8 n x kbar blocks per site) bound the count
         NBLD = 8;
-        const double per = 16.0 * ((double)op.spat.nnz + 4.0 * n + (two_level ? 9.0 : 1.0) * n * P.kbar_max);
+        const double per = 16.0 * ((double)op.spat.nnz + 3.0 * n + m + (two_level ? 9.0 : 1.0) * n * P.kbar_max);
         NS = (int)std::max(2.0, std::min((double)t + NBLD, std::min(64.0, P.site_mem_gb * 1e9 / 5.0 / per)));
         Slu.alloc((size_t)NS * op.spat.nnz);
-        Svec.alloc((size_t)NS * 4 * n);
+        Svec.alloc((size_t)NS * (3 * n + m));
         pS.alloc((size_t)NS * n * std::max(P.kbar_max, 1));
         d_slotz.alloc(NS);
         d_icbad.alloc(NS);

@@ -133,7 +133,32 @@ void Engine::lob_step(const std::vector<int>& L, uint64_t seed, std::vector<int>
     op_apply(false, L, S.p + (size_t)n * r, sS, n, CS.p + (size_t)m * r, sC, m, r);
     BlockList Lcs = bl_empty(m);
     bl_add(Lcs, CS.p, sC, m, 0, d_cdimt.p, 1);
-    r_factor(d_list.p, nt, Lcs, r3, d_cdimt.p, 1, 0, Rsm.p, (int64_t)9 * r * r, r3);
+    // R of C(z) S: a Gram matrix in double perturbs an eigenvalue xi^2 by
+    // about eps ||C(z) S||^2, i.e. xi by eps (||C|| + |z|)^2 / (2 xi); for a
+    // tile whose previous smallest Ritz value is at least 1e-4 (||C|| + |z|)
+    // that is below 1e-12 (||C|| + |z|), four orders under the tolerance, and
+    // the double Gram is used; otherwise (and on a refinement's first
+    // iteration) the Gram is accumulated in double-double
+    {
+        std::vector<int> Ldd, Lpl;
+        for (int t : L) {
+            const double nz = op.normC + sqrt(zabs2(h_zt[t]));
+            const bool proj = two_level && phase[t];     // Mbar(z): another scale, keep double-double
+            if (!proj && lob_it[t] >= 1 && lob_xi[t] >= 1e-4 * nz) Lpl.push_back(t);
+            else Ldd.push_back(t);
+        }
+        if (Lpl.empty()) {
+            r_factor(d_list.p, nt, Lcs, r3, d_cdimt.p, 1, 0, Rsm.p, (int64_t)9 * r * r, r3);
+        } else {
+            upload_list(Lpl, d_listPL);
+            r_factor(d_listPL.p, (int)Lpl.size(), Lcs, r3, d_cdimt.p, 1, 0, Rsm.p, (int64_t)9 * r * r, r3, nullptr,
+                     nullptr, false);
+            if (!Ldd.empty()) {
+                upload_list(Ldd, d_listDD);
+                r_factor(d_listDD.p, (int)Ldd.size(), Lcs, r3, d_cdimt.p, 1, 0, Rsm.p, (int64_t)9 * r * r, r3);
+            }
+        }
+    }
     for (int t : L) nop[t] = 0;
     RRArgs ra;
     memset(&ra, 0, sizeof(ra));

@@ -1,4 +1,4 @@
-// Sparse base preconditioner sites (square CSR C): the pattern of N = C^* C,
+// Sparse base preconditioner sites (CSR C, m >= n): the pattern of N = C^* C,
 // its colour ordering and the contribution lists that form N(z) from the
 // values of C (host, once per handle), and the construction of sites: the
 // incomplete Cholesky factorization of N(z_dag) + alpha I (Sec. 3 and 4; the
@@ -197,7 +197,8 @@ std::vector<int> Engine::build_sparse_sites(const std::vector<zd>& sites, const 
     const int* dl = d_listB.p;
     // power iterations on F^{-1} F^{-*} (gamma^2) and on
     // Tbar(z_dag) = F^{-*} N(z_dag) F^{-1} (lambda_n^dagger)
-    const int64_t sv = 4 * n, sw = (int64_t)n * KB;
+    // per slot: x (n), F^{-1} x (n), C(z) F^{-1} x (m), C(z)^* C(z) F^{-1} x (n)
+    const int64_t sv = 3 * n + m, sw = (int64_t)n * KB;
     const int r3 = 3 * r;
     std::vector<double> g2(ns, 0.0), ln(ns, 0.0);
     for (int pass = 0; pass < 2; ++pass) {
@@ -208,9 +209,10 @@ std::vector<int> Engine::build_sparse_sites(const std::vector<zd>& sites, const 
                 launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 0, Svec.p + n, sv, n, Svec.p, sv, n, 1, pS.p, sw, st);
             } else {
                 launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 0, Svec.p, sv, n, Svec.p + n, sv, n, 1, pS.p, sw, st);
-                apply(false, dl, ns, Svec.p + n, sv, n, Svec.p + 2 * n, sv, n, 1, d_slotz.p);
-                apply(true, dl, ns, Svec.p + 2 * n, sv, n, Svec.p + 3 * n, sv, n, 1, d_slotz.p);
-                launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 1, Svec.p + 3 * n, sv, n, Svec.p, sv, n, 1, pS.p, sw, st);
+                apply(false, dl, ns, Svec.p + n, sv, n, Svec.p + 2 * n, sv, m, 1, d_slotz.p);
+                apply(true, dl, ns, Svec.p + 2 * n, sv, m, Svec.p + 2 * n + m, sv, n, 1, d_slotz.p);
+                launch_ic_solve(dl, ns, nullptr, sp, Slu.p, 1, Svec.p + 2 * n + m, sv, n, Svec.p, sv, n, 1, pS.p,
+                                sw, st);
             }
             BlockList Lp = bl_empty(n);
             bl_add(Lp, Svec.p, sv, n, 1, nullptr, 0);

@@ -17,21 +17,22 @@ __device__ __host__ inline int bl_cols(const BlockList& L, int b, int t)
 {
     return L.dims[b] ? L.dims[b][bl_t(L, b, t)] * L.mul[b] : L.ncols[b];
 }
-// element (i, c) of the block list for tile t (zero beyond a block's rows)
-__device__ inline zd bl_get(const BlockList& L, int t, int64_t i, int c)
+// column c of tile t: pointer to its first element and the rows stored
+// (NULL beyond the tile's columns)
+__device__ inline const zd* bl_col(const BlockList& L, int t, int c, int64_t& rows)
 {
     for (int b = 0; b < L.nb; ++b) {
-        int nc = bl_cols(L, b, t);
+        const int nc = bl_cols(L, b, t);
         if (c < nc) {
-            int64_t br = L.brows[b] ? L.brows[b] : L.rows;
-            if (i >= br) return zmake(0.0, 0.0);
+            rows = L.brows[b] ? L.brows[b] : L.rows;
             const int tb = bl_t(L, b, t);
-            int c0 = L.coff[b] ? L.coff[b][tb] * L.coffmul[b] : 0;
-            return L.ptr[b][(size_t)tb * L.stride[b] + i + (size_t)(c + c0) * L.ld[b]];
+            const int c0 = L.coff[b] ? L.coff[b][tb] * L.coffmul[b] : 0;
+            return L.ptr[b] + (size_t)tb * L.stride[b] + (size_t)(c + c0) * L.ld[b];
         }
         c -= nc;
     }
-    return zmake(0.0, 0.0);
+    rows = 0;
+    return nullptr;
 }
 __device__ inline int bl_total(const BlockList& L, int t)
 {
@@ -48,6 +49,9 @@ __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
 {
     __shared__ zd As[32][33];
     __shared__ zd Bs[32][33];
+    __shared__ const zd* pa[32];
+    __shared__ const zd* pb[32];
+    __shared__ int64_t na[32], nb_[32];
     const int chunk = blockIdx.x;
     const int ot = blockIdx.y;
     const int ti = ot / ntj, tj = ot % ntj;
@@ -60,6 +64,17 @@ __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
     const int64_t r0 = (int64_t)chunk * a.chunk_rows;
     int64_t r1 = r0 + a.chunk_rows;
     if (r1 > a.A.rows) r1 = a.A.rows;
+    // the 32 + 32 columns of this output tile, resolved once
+    if (tid < 32) {
+        const int g = ti * 32 + tid;
+        pa[tid] = (g < ca) ? bl_col(a.A, tile, g, na[tid]) : nullptr;
+        if (g >= ca) na[tid] = 0;
+    } else if (tid < 64) {
+        const int c = tid - 32, g = tj * 32 + c;
+        pb[c] = (g < cb) ? bl_col(a.B, tile, g, nb_[c]) : nullptr;
+        if (g >= cb) nb_[c] = 0;
+    }
+    __syncthreads();
     const int li = tid & 31, lj0 = tid >> 5;   // outputs (li, lj0 + 8 q)
     zacc acc[4];
     zd accd[4];
@@ -69,9 +84,8 @@ __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
         for (int e = tid; e < 32 * 32; e += NT) {
             int rr = e & 31, cc = e >> 5;
             int64_t i = rb + rr;
-            int ga = ti * 32 + cc, gb = tj * 32 + cc;
-            As[rr][cc] = (i < r1 && ga < ca) ? bl_get(a.A, tile, i, ga) : zmake(0.0, 0.0);
-            Bs[rr][cc] = (i < r1 && gb < cb) ? bl_get(a.B, tile, i, gb) : zmake(0.0, 0.0);
+            As[rr][cc] = (i < r1 && i < na[cc]) ? pa[cc][i] : zmake(0.0, 0.0);
+            Bs[rr][cc] = (i < r1 && i < nb_[cc]) ? pb[cc][i] : zmake(0.0, 0.0);
         }
         __syncthreads();
         int nr = (int)((r1 - rb) < 32 ? (r1 - rb) : 32);
@@ -123,7 +137,14 @@ __global__ void __launch_bounds__(NT) k_gram_reduce(GramArgs a)
             if (r0 >= a.A.rows) break;
             s = zadd(s, ((const zd*)a.part)[base + (size_t)c * a.part_stride]);
         }
-        ((zd*)a.out)[(size_t)tile * a.strideOut + gi + (size_t)gj * a.ldOut] = s;
+        if (a.out_dd) {
+            zdd v;
+            v.x = dd_make(s.x);
+            v.y = dd_make(s.y);
+            ((zdd*)a.out)[(size_t)tile * a.strideOut + gi + (size_t)gj * a.ldOut] = v;
+        } else {
+            ((zd*)a.out)[(size_t)tile * a.strideOut + gi + (size_t)gj * a.ldOut] = s;
+        }
     }
 }
 
@@ -226,7 +247,10 @@ __global__ void __launch_bounds__(NT) k_colnorm_part(NormArgs a)
     if (r1 > a.A.rows) r1 = a.A.rows;
     for (int c = w; c < ca; c += NT / 64) {
         double s = 0;
-        for (int64_t i = r0 + lane; i < r1; i += 64) s += zabs2(bl_get(a.A, tile, i, c));
+        int64_t nr = 0;
+        const zd* col = bl_col(a.A, tile, c, nr);
+        const int64_t re = r1 < nr ? r1 : nr;
+        for (int64_t i = r0 + lane; i < re; i += 64) s += zabs2(col[i]);
         s = wave_sum(s);
         if (lane == 0) a.part[((size_t)tix * a.nchunks + chunk) * a.camax + c] = s;
     }

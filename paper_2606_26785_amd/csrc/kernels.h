@@ -96,6 +96,7 @@ struct GramArgs {
     int nchunks;
     int dd;
     int hermitian_upper_only;
+    int out_dd;                  // dd == 0: write the sums as double-double (low parts zero)
 };
 void launch_gram(GramArgs& a, hipStream_t s);
 size_t gram_part_bytes(int64_t rows, int camax, int cbmax, int ntiles, int dd, int chunk_rows);

@@ -146,9 +146,7 @@ ps_status ps_create(const ps_matrix_desc* d, const ps_params* params, void* hip_
         !(p.tol_abs >= 0) || p.tol_abs > 1e-6 || p.esc_iters < 0)
         return fail(PS_EINVAL, "bad tolerances");
     if (p.precond > 2 || p.precond < -1) return fail(PS_EINVAL, "precond must be -1, 0, 1 or 2");
-    if (p.precond >= 1 && d->kind != PS_DENSE && d->m != d->n)
-        return fail(PS_EUNSUPPORTED, "the sparse base preconditioner needs a square matrix");
-    const int pc = p.precond < 0 ? (d->kind == PS_DENSE ? 1 : (d->m == d->n ? 2 : 0)) : p.precond;
+    const int pc = p.precond < 0 ? (d->kind == PS_DENSE ? 1 : 2) : p.precond;
     if (pc == 2 && p.rbar != p.r)
         return fail(PS_EINVAL, "the two-level preconditioner runs its projection LOBPCG with block rbar = r");
     if (!(p.eta_proj > 0) || !(p.tau_min > 0) || !(p.tau_max > 1.0) || !(p.reg_base >= 0) || p.reg_base > 1.0)
