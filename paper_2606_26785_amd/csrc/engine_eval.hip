@@ -804,13 +804,45 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                 }
             }
             if (!fsites.empty()) {
-                std::vector<char> pd;
-                std::vector<int> got = build_precond(fsites, &fmus, &pd, true);
-                // a tile whose shifted sites are all indefinite has an
-                // eigenvalue of N(z) far below xi^2 (xi is not yet
-                // sigma_min): it gets the site N(z) + delta I at z instead
-                // (kind 4: unlike kind 2 it leaves later shifts possible, for
-                // when xi has come down to the bottom of a cluster)
+                // the shifts are tried closest first: kind 1 (with the exact
+                // sites of kind 2) in one batch, kind 3 only for the tiles
+                // whose kind-1 factorization was indefinite, and a tile whose
+                // shifted sites are all indefinite has an eigenvalue of N(z)
+                // far below xi^2 (xi is not yet sigma_min): it gets the site
+                // N(z) + delta I at z (kind 4: unlike kind 2 it leaves later
+                // shifts possible, for when xi has come down to the bottom of
+                // a cluster)
+                std::vector<int> got(fsites.size(), -1);
+                std::vector<char> pd(fsites.size(), 0);
+                std::vector<int> idx3(T, -1);
+                auto build_stage = [&](const std::vector<int>& idx) {
+                    if (idx.empty()) return;
+                    std::vector<zd> ss;
+                    std::vector<double> mm;
+                    for (int i : idx) { ss.push_back(fsites[i]); mm.push_back(fmus[i]); }
+                    std::vector<char> pp;
+                    std::vector<int> gg = build_precond(ss, &mm, &pp, true);
+                    for (size_t k = 0; k < idx.size(); ++k) { got[idx[k]] = gg[k]; pd[idx[k]] = pp[k]; }
+                    // indefinite shifted sites are of no use: free their slots
+                    for (int i : idx)
+                        if (got[i] >= 0 && !pd[i] && (fkind[i] == 1 || fkind[i] == 3)) {
+                            slot_valid[got[i]] = 0;
+                            got[i] = -1;
+                        }
+                };
+                {
+                    std::vector<int> st1;
+                    for (size_t i = 0; i < fsites.size(); ++i) {
+                        if (fkind[i] == 3) idx3[fown[i]] = (int)i;
+                        else st1.push_back((int)i);
+                    }
+                    build_stage(st1);
+                    std::vector<int> st3;
+                    for (size_t i = 0; i < fsites.size(); ++i)
+                        if (fkind[i] == 1 && got[i] < 0 && idx3[fown[i]] >= 0 && !certified[fown[i]])
+                            st3.push_back(idx3[fown[i]]);
+                    build_stage(st3);
+                }
                 {
                     std::vector<char> has_pd(T, 0), asked(T, 0);
                     for (size_t i = 0; i < fsites.size(); ++i) {
@@ -828,13 +860,6 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                             xo.push_back(t);
                         }
                     if (!xs.empty()) {
-                        // the indefinite shifted sites are of no use: free
-                        // their slots first
-                        for (size_t i = 0; i < fsites.size(); ++i)
-                            if (got[i] >= 0 && !pd[i] && (fkind[i] == 1 || fkind[i] == 3)) {
-                                slot_valid[got[i]] = 0;
-                                got[i] = -1;
-                            }
                         std::vector<char> pd2;
                         std::vector<int> got2 = build_precond(xs, &xm, &pd2, true);
                         for (size_t i = 0; i < xs.size(); ++i) {
