@@ -43,57 +43,77 @@ __device__ inline int bl_total(const BlockList& L, int t)
 
 // ---------------------------------------------------------------------------
 // Gram: part[(tile, chunk)] = A[rows of chunk]^* B[rows of chunk] for one
-// 32 x 32 output tile per workgroup (grid: chunks x out-tiles x tiles).
-template <int DD>
+// CA x CB output tile per workgroup (grid: chunks x out-tiles x tiles), CA and
+// CB the column counts rounded up to 8, 16 or 32, so that narrow blocks do
+// not compute padding.  Each thread owns Q outputs; when the tile has fewer
+// outputs than threads, G groups of threads split the staged rows and their
+// sums are added at the end.
+template <int DD, int CA, int CB>
 __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
 {
-    __shared__ zd As[32][33];
-    __shared__ zd Bs[32][33];
-    __shared__ const zd* pa[32];
-    __shared__ const zd* pb[32];
-    __shared__ int64_t na[32], nb_[32];
+    constexpr int O = CA * CB;
+    constexpr int Q = O >= NT ? O / NT : 1;
+    constexpr int G = O >= NT ? 1 : NT / O;
+    constexpr int SR = 32;                       // rows per staging step
+    __shared__ zd As[SR][CA + 1];
+    __shared__ zd Bs[SR][CB + 1];
+    __shared__ const zd* pa[CA];
+    __shared__ const zd* pb[CB];
+    __shared__ int64_t na[CA], nb_[CB];
     const int chunk = blockIdx.x;
     const int ot = blockIdx.y;
     const int ti = ot / ntj, tj = ot % ntj;
     const int tix = blockIdx.z;
     const int tile = a.list[tix];
     const int ca = bl_total(a.A, tile), cb = bl_total(a.B, tile);
-    if (ti * 32 >= ca || tj * 32 >= cb) return;
-    if (a.hermitian_upper_only && tj < ti) return;
+    if (ti * CA >= ca || tj * CB >= cb) return;
+    if (a.hermitian_upper_only && tj * CB + CB - 1 < ti * CA) return;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)chunk * a.chunk_rows;
     int64_t r1 = r0 + a.chunk_rows;
     if (r1 > a.A.rows) r1 = a.A.rows;
-    // the 32 + 32 columns of this output tile, resolved once
-    if (tid < 32) {
-        const int g = ti * 32 + tid;
+    // the CA + CB columns of this output tile, resolved once
+    if (tid < CA) {
+        const int g = ti * CA + tid;
         pa[tid] = (g < ca) ? bl_col(a.A, tile, g, na[tid]) : nullptr;
         if (g >= ca) na[tid] = 0;
-    } else if (tid < 64) {
-        const int c = tid - 32, g = tj * 32 + c;
+    } else if (tid < CA + CB) {
+        const int c = tid - CA, g = tj * CB + c;
         pb[c] = (g < cb) ? bl_col(a.B, tile, g, nb_[c]) : nullptr;
         if (g >= cb) nb_[c] = 0;
     }
     __syncthreads();
-    const int li = tid & 31, lj0 = tid >> 5;   // outputs (li, lj0 + 8 q)
-    zacc acc[4];
-    zd accd[4];
-    for (int q = 0; q < 4; ++q) { zacc_init(acc[q]); accd[q] = zmake(0.0, 0.0); }
-    for (int64_t rb = r0; rb < r1; rb += 32) {
-        // stage 32 rows x 32 columns of A and B
-        for (int e = tid; e < 32 * 32; e += NT) {
-            int rr = e & 31, cc = e >> 5;
-            int64_t i = rb + rr;
+    int oi[Q], oj[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int o = (G == 1) ? tid + NT * q : tid % O;
+        oi[q] = o % CA;
+        oj[q] = o / CA;
+    }
+    const int grp = (G == 1) ? 0 : tid / O;
+    zacc acc[Q];
+    zd accd[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) { zacc_init(acc[q]); accd[q] = zmake(0.0, 0.0); }
+    for (int64_t rb = r0; rb < r1; rb += SR) {
+        // stage SR rows of the CA + CB columns (consecutive threads take
+        // consecutive rows of one column)
+        for (int e = tid; e < SR * CA; e += NT) {
+            const int rr = e % SR, cc = e / SR;
+            const int64_t i = rb + rr;
             As[rr][cc] = (i < r1 && i < na[cc]) ? pa[cc][i] : zmake(0.0, 0.0);
+        }
+        for (int e = tid; e < SR * CB; e += NT) {
+            const int rr = e % SR, cc = e / SR;
+            const int64_t i = rb + rr;
             Bs[rr][cc] = (i < r1 && i < nb_[cc]) ? pb[cc][i] : zmake(0.0, 0.0);
         }
         __syncthreads();
-        int nr = (int)((r1 - rb) < 32 ? (r1 - rb) : 32);
-        for (int rr = 0; rr < nr; ++rr) {
-            zd x = As[rr][li];
+        const int nr = (int)((r1 - rb) < SR ? (r1 - rb) : SR);
+        for (int rr = grp; rr < nr; rr += G) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                zd y = Bs[rr][lj0 + 8 * q];
+            for (int q = 0; q < Q; ++q) {
+                const zd x = As[rr][oi[q]], y = Bs[rr][oj[q]];
                 if (DD) zacc_cfma(acc[q], x, y);
                 else zcfma(accd[q], x, y);
             }
@@ -101,12 +121,30 @@ __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
         __syncthreads();
     }
     const size_t base = ((size_t)tix * a.nchunks + chunk) * a.part_stride;
-    for (int q = 0; q < 4; ++q) {
-        int gi = ti * 32 + li, gj = tj * 32 + lj0 + 8 * q;
+    if (G == 1) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int gi = ti * CA + oi[q], gj = tj * CB + oj[q];
+            if (gi < ca && gj < cb) {
+                const size_t off = base + gi + (size_t)gj * a.camax;
+                if (DD) ((zdd*)a.part)[off] = zacc_value(acc[q]);
+                else ((zd*)a.part)[off] = accd[q];
+            }
+        }
+        return;
+    }
+    // G > 1: add the groups' sums (double-double for DD)
+    __shared__ zdd red[(O < NT) ? NT : 1];
+    red[tid] = DD ? zacc_value(acc[0]) : zdd{dd_make(accd[0].x), dd_make(accd[0].y)};
+    __syncthreads();
+    if (grp == 0) {
+        zdd sum = red[tid];
+        for (int h = 1; h < G; ++h) sum = zdd_add(sum, red[tid + h * O]);
+        const int gi = ti * CA + oi[0], gj = tj * CB + oj[0];
         if (gi < ca && gj < cb) {
-            size_t off = base + gi + (size_t)gj * a.camax;
-            if (DD) ((zdd*)a.part)[off] = zacc_value(acc[q]);
-            else ((zd*)a.part)[off] = accd[q];
+            const size_t off = base + gi + (size_t)gj * a.camax;
+            if (DD) ((zdd*)a.part)[off] = sum;
+            else ((zd*)a.part)[off] = zmake(sum.x.hi + sum.x.lo, sum.y.hi + sum.y.lo);
         }
     }
 }
@@ -159,16 +197,31 @@ void launch_gram(GramArgs& a, hipStream_t s)
     if (a.ntiles <= 0) return;
     a.nchunks = (int)((a.A.rows + a.chunk_rows - 1) / a.chunk_rows);
     a.part_stride = (int64_t)a.camax * a.cbmax;
-    int nti = (a.camax + 31) / 32, ntj = (a.cbmax + 31) / 32;
+    const int ta = a.camax <= 8 ? 8 : (a.camax <= 16 ? 16 : 32);
+    const int tb = a.cbmax <= 8 ? 8 : (a.cbmax <= 16 ? 16 : 32);
+    const int nti = (a.camax + ta - 1) / ta, ntj = (a.cbmax + tb - 1) / tb;
     dim3 g1(a.nchunks, nti * ntj, a.ntiles);
     dim3 g2((a.camax * a.cbmax + NT - 1) / NT, a.ntiles);
+#define GRAM_PART(DDV, X, Y) hipLaunchKernelGGL((k_gram_part<DDV, X, Y>), g1, dim3(NT), 0, s, a, ntj)
+#define GRAM_ROW(DDV, X)                        \
+    do {                                        \
+        if (tb == 8) GRAM_PART(DDV, X, 8);      \
+        else if (tb == 16) GRAM_PART(DDV, X, 16); \
+        else GRAM_PART(DDV, X, 32);             \
+    } while (0)
     if (a.dd) {
-        hipLaunchKernelGGL(k_gram_part<1>, g1, dim3(NT), 0, s, a, ntj);
+        if (ta == 8) GRAM_ROW(1, 8);
+        else if (ta == 16) GRAM_ROW(1, 16);
+        else GRAM_ROW(1, 32);
         hipLaunchKernelGGL(k_gram_reduce<1>, g2, dim3(NT), 0, s, a);
     } else {
-        hipLaunchKernelGGL(k_gram_part<0>, g1, dim3(NT), 0, s, a, ntj);
+        if (ta == 8) GRAM_ROW(0, 8);
+        else if (ta == 16) GRAM_ROW(0, 16);
+        else GRAM_ROW(0, 32);
         hipLaunchKernelGGL(k_gram_reduce<0>, g2, dim3(NT), 0, s, a);
     }
+#undef GRAM_ROW
+#undef GRAM_PART
 }
 
 // ---------------------------------------------------------------------------
