@@ -48,6 +48,14 @@ ps_status ps_debug_site(ps_matrix* h, double* dreg, double* gamma);
 ps_status ps_debug_sparse_site(ps_matrix* h, double z_re, double z_im, int32_t trans, const double* X, int32_t w,
                                double* Y, double* alpha);
 
+/* One inertia test (the certificate of a clustered refinement): pd = 1 when
+ * every pivot of the Cholesky factorization of N(z) - mu I is positive,
+ * i.e. sigma_min(C - z I)^2 > mu; dense handles factor N(z) - mu I densely,
+ * CSR handles whose N = C^* C has bandwidth <= 63 by a band Cholesky.
+ * Errors: PS_EUNSUPPORTED (no preconditioner, or a CSR matrix without a
+ * narrow band), PS_EDEVICE. */
+ps_status ps_debug_inertia(ps_matrix* h, double z_re, double z_im, double mu, int32_t* pd);
+
 /* The recycled singular store of `tile` as the last ps_eval left it (Sec.
  * 2.2): its dimension k, the orthonormal basis V (n x k_max), W1 = C V
  * (m x k_max), W3 = C^* C V and W4 = C^* S V (n x k_max), and the cached R

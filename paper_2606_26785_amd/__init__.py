@@ -124,6 +124,8 @@ def load():
     lib.ps_debug_sparse_site.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, ctypes.c_int32,
                                          P, P]
     lib.ps_debug_sparse_site.restype = ctypes.c_int
+    lib.ps_debug_inertia.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+    lib.ps_debug_inertia.restype = ctypes.c_int
     lib.ps_debug_norm.argtypes = [P]
     lib.ps_debug_norm.restype = ctypes.c_double
     _lib = lib
@@ -300,6 +302,15 @@ def debug_sparse_site(mat: Matrix, z: complex, X: np.ndarray, trans: int = 0):
     _check(load().ps_debug_sparse_site(mat.handle, float(np.real(z)), float(np.imag(z)), int(trans), _ptr(X),
                                        X.shape[1], _ptr(Y), _ptr(a)), "ps_debug_sparse_site")
     return Y, float(a[0])
+
+
+def debug_inertia(mat: Matrix, z: complex, mu: float) -> bool:
+    """True when N(z) - mu I is positive definite by the library's inertia
+    test (test hook)."""
+    pd = np.zeros(1, dtype=np.int32)
+    _check(load().ps_debug_inertia(mat.handle, float(np.real(z)), float(np.imag(z)), float(mu), _ptr(pd)),
+           "ps_debug_inertia")
+    return bool(pd[0])
 
 
 def debug_order(nx: int, ny: int, tx: int, ty: int, b: int, traversal: int):

@@ -254,6 +254,15 @@ struct Engine {
     DBuf<zd> Slu, Svec, pS, d_slotz, Tq;
     DBuf<int> d_listC;
     DBuf<int> d_icbad;          // per slot: a pivot of its incomplete Cholesky was not positive
+    // inertia tests for a CSR C whose N = C^* C has bandwidth band_b <= 63 in
+    // the natural order (-1: no such tests): contribution lists of the band
+    // entries (row j, offset d) at j (band_b + 1) + d, per-test band storage
+    int band_b = -1;
+    DBuf<int64_t> bn_cp, bn_ca, bn_cb;
+    DBuf<zd> bn_W, bn_z;
+    DBuf<double> bn_mu;
+    DBuf<int> bn_bad, bn_list;
+    void band_inertia(const std::vector<zd>& zs, const std::vector<double>& mus, std::vector<char>& pd);
     DBuf<double> d_alpha;       // per slot: diagonal shift alpha of N(z_dag) + alpha I
     std::vector<double> slot_alpha;
     void build_sparse_pattern();        // colouring and patterns (host, once per handle)

@@ -726,7 +726,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
         // cannot resolve them) get an exact site N(z) + delta I at their own
         // point instead.  slack bounds the rounding of forming N(z) and of the
         // Cholesky factorization.
-        if (use_prec && P.esc_iters > 0 && op.kind == PS_DENSE) {
+        if (use_prec && P.esc_iters > 0 && (op.kind == PS_DENSE || band_b >= 0)) {
             std::vector<char> isfin(T, 0);
             for (int t : fin) isfin[t] = 1;
             std::vector<zd> fsites;
@@ -755,7 +755,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                         cert_since[t] = loops;
                         pending.push_back(t);
                     }
-                    if (period && cert_fail[t] >= 2 && !site_exact[t]) {
+                    if (period && cert_fail[t] >= 2 && !site_exact[t] && op.kind == PS_DENSE) {
                         fsites.push_back(z); fmus.push_back((xi - 64.0 * tau_c) * (xi - 64.0 * tau_c));
                         fown.push_back(t); fkind.push_back(1);
                         if (xi > 4096.0 * tau_c) {
@@ -763,7 +763,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                             fown.push_back(t); fkind.push_back(3);
                         }
                     }
-                } else if (period && !site_exact[t]) {
+                } else if (period && !site_exact[t] && op.kind == PS_DENSE) {
                     fsites.push_back(z); fmus.push_back(0.0); fown.push_back(t); fkind.push_back(2);
                 }
             }

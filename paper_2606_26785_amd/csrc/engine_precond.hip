@@ -200,11 +200,13 @@ std::vector<int> Engine::build_precond(const std::vector<zd>& sites, const std::
     std::vector<int> out;
     if (pd) pd->assign(sites.size(), 0);
     if (op.kind != PS_DENSE) {
-        // sparse sites: incomplete Cholesky of N(z_dag) + alpha I (shifts and inertia
-        // tests are dense-only: a factorisation for a test is reported as
-        // not positive definite, so no certificate is taken from it)
+        // sparse sites: incomplete Cholesky of N(z_dag) + alpha I.  Inertia
+        // tests need an exact factorization: a band Cholesky when N has a
+        // narrow band, otherwise the test is reported as not positive
+        // definite, so no certificate is taken from it
         if (cert_only) {
             out.assign(sites.size(), -1);
+            if (pd && mu && band_b >= 0) band_inertia(sites, *mu, *pd);
             return out;
         }
         std::vector<zd> zs_ok;

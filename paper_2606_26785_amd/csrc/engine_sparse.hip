@@ -8,6 +8,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -142,6 +143,45 @@ void Engine::build_sparse_pattern()
         HIPCHK(hipMemcpy(op.sp_ca.p, ca.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(op.sp_cb.p, cb.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice));
     }
+    // narrow band of N in the natural order: exact inertia tests by a band
+    // Cholesky (the entries (j, j + d), d <= b, from the same row pairs)
+    {
+        int64_t b = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            row_entries(i, E);
+            int32_t lo = INT32_MAX, hi = -1;
+            for (auto& a : E) { lo = std::min(lo, a.first); hi = std::max(hi, a.first); }
+            if (hi >= 0) b = std::max<int64_t>(b, hi - lo);
+        }
+        band_b = (b <= 63) ? (int)b : -1;
+        if (band_b >= 0) {
+            const int64_t bw = band_b + 1, ne = nn * bw;
+            std::vector<int64_t> bcp(ne + 1, 0);
+            for (int64_t i = 0; i < m; ++i) {
+                row_entries(i, E);
+                for (auto& a : E)
+                    for (auto& c : E)
+                        if (c.first >= a.first) bcp[(int64_t)a.first * bw + (c.first - a.first) + 1]++;
+            }
+            for (int64_t e = 0; e < ne; ++e) bcp[e + 1] += bcp[e];
+            std::vector<int64_t> ba(std::max<int64_t>(bcp[ne], 1)), bb(std::max<int64_t>(bcp[ne], 1));
+            std::vector<int64_t> fill(bcp.begin(), bcp.end() - 1);
+            for (int64_t i = 0; i < m; ++i) {
+                row_entries(i, E);
+                for (auto& a : E)
+                    for (auto& c : E)
+                        if (c.first >= a.first) {
+                            const int64_t o = fill[(int64_t)a.first * bw + (c.first - a.first)]++;
+                            ba[o] = a.second;
+                            bb[o] = c.second;
+                        }
+            }
+            bn_cp.alloc(ne + 1); bn_ca.alloc(ba.size()); bn_cb.alloc(bb.size());
+            HIPCHK(hipMemcpy(bn_cp.p, bcp.data(), sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(bn_ca.p, ba.data(), sizeof(int64_t) * ba.size(), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(bn_cb.p, bb.data(), sizeof(int64_t) * bb.size(), hipMemcpyHostToDevice));
+        }
+    }
     op.sp_cptr = cptr;
     SparsePattern& sp = op.spat;
     sp.n = nn;
@@ -237,4 +277,37 @@ std::vector<int> Engine::build_sparse_sites(const std::vector<zd>& sites, const 
         ok.push_back(s);
     }
     return ok;
+}
+
+// Inertia tests N(z_i) - mu_i I > 0 for a narrow-band CSR C (band_b >= 0),
+// up to 32 at a time: pd[i] = 1 when every pivot of the band Cholesky is
+// positive.
+void Engine::band_inertia(const std::vector<zd>& zs, const std::vector<double>& mus, std::vector<char>& pd)
+{
+    pd.assign(zs.size(), 0);
+    if (band_b < 0 || zs.empty()) return;
+    const int64_t bw = band_b + 1;
+    const int cap = 32;
+    if (bn_W.n < (size_t)cap * n * bw) {
+        HIPCHK(hipStreamSynchronize(st));
+        bn_W.alloc((size_t)cap * n * bw);
+        bn_z.alloc(cap); bn_mu.alloc(cap); bn_bad.alloc(cap); bn_list.alloc(cap);
+        std::vector<int> id(cap);
+        for (int i = 0; i < cap; ++i) id[i] = i;
+        HIPCHK(hipMemcpy(bn_list.p, id.data(), sizeof(int) * cap, hipMemcpyHostToDevice));
+    }
+    for (size_t b0 = 0; b0 < zs.size(); b0 += cap) {
+        const int nb = (int)std::min<size_t>(cap, zs.size() - b0);
+        std::vector<zd> hz(zs.begin() + b0, zs.begin() + b0 + nb);
+        std::vector<double> hm(mus.begin() + b0, mus.begin() + b0 + nb);
+        std::vector<int> zero(nb, 0), bad(nb, 0);
+        h2d(bn_z.p, hz.data(), sizeof(zd) * nb);
+        h2d(bn_mu.p, hm.data(), sizeof(double) * nb);
+        h2d(bn_bad.p, zero.data(), sizeof(int) * nb);
+        launch_band_inertia(bn_list.p, nb, bn_z.p, bn_mu.p, bn_cp.p, bn_ca.p, bn_cb.p, op.v.p, n, band_b, bn_W.p,
+                            n * bw, 0.0, bn_bad.p, st);
+        HIPCHK(hipMemcpyAsync(bad.data(), bn_bad.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i < nb; ++i) pd[b0 + i] = bad[i] ? 0 : 1;
+    }
 }

@@ -1,4 +1,4 @@
-// Sparse base preconditioner for square CSR C (Sec. 3, the base K of eq.
+// Sparse base preconditioner for CSR C (Sec. 3, the base K of eq.
 // (twolevel); Sec. 4 uses an incomplete Cholesky factorization of N(z_dag)):
 // K = L D L^* ~ N(z_dag) + alpha I, the incomplete Cholesky factorization
 // without fill of the Hermitian positive definite N(z_dag) + alpha I on the
@@ -235,4 +235,74 @@ void launch_ic_solve(const int* list, int ni, const int* site, const SparsePatte
         hipLaunchKernelGGL(k_scale_dhalf, gp, dim3(NT), 0, s, list, site, sp.diag, lu, sp.nnz, n, w, T, ts, n);
         launch_copy_cols(list, ni, T, ts, n, Y, ys, ldy, n, w, s);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Inertia test for a CSR C whose N = C^* C has a narrow band (bandwidth
+// b <= 63 in the natural order): the exact Cholesky factorization of the
+// band of N(z) - mu I, one workgroup (one wave) per test.  Band storage, row
+// j: entries (j, j + d), d = 0..b, at W[j (b + 1) + d], formed from the
+// contribution lists of the band (as k_icn_form does for the incomplete
+// factor); then for j = 0, 1, ...: thread d forms
+// s_d = A(j, j+d) - sum_{k = j-b}^{j-1} conj(R(k, j)) R(k, j+d), the pivot
+// s_0 must be positive (else notpd), and R(j, j+d) = s_d / sqrt(s_0).
+// Every pivot positive means N(z) - mu I is positive definite.
+__global__ void __launch_bounds__(64) k_band_inertia(const int* list, const zd* zsite, const double* mu,
+                                                     const int64_t* cptr, const int64_t* ca, const int64_t* cb,
+                                                     const zd* vC, int64_t n, int b, zd* W, int64_t wstride,
+                                                     double floor_rel, int* notpd)
+{
+    const int s = list[blockIdx.x];
+    const int tid = threadIdx.x;
+    const zd z = zsite[s];
+    const int bw = b + 1;
+    zd* R = W + (size_t)s * wstride;
+    // form the band of N(z) - mu I
+    for (int64_t e = tid; e < n * bw; e += 64) {
+        zd acc = zmake(0.0, 0.0);
+        for (int64_t q = cptr[e]; q < cptr[e + 1]; ++q) zcfma(acc, icn_val(vC, ca[q], z), icn_val(vC, cb[q], z));
+        if (e % bw == 0) acc.x -= mu[s];
+        R[e] = acc;
+    }
+    __syncthreads();
+    __shared__ double piv;
+    __shared__ int bad;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int64_t j = 0; j < n; ++j) {
+        const int d = tid;
+        zd sacc = zmake(0.0, 0.0);
+        const bool live = d <= b && j + d < n;
+        if (live) {
+            sacc = R[j * bw + d];
+            const int64_t k0 = j - b > 0 ? j - b : 0;
+            for (int64_t k = k0; k < j; ++k) {
+                const int o = (int)(j - k);            // R(k, j) at offset j - k of row k
+                if (o + d > b) continue;               // R(k, j + d) outside the band
+                sacc = zsub(sacc, zcmul(R[k * bw + o], R[k * bw + o + d]));
+            }
+        }
+        if (d == 0) {
+            const double fl = floor_rel;
+            double p = sacc.x;
+            if (!(p > fl)) {
+                bad = 1;
+                p = fl > 0.0 ? fl : 1e-300;
+            }
+            piv = sqrt(p);
+        }
+        __syncthreads();
+        if (live) R[j * bw + d] = (d == 0) ? zmake(piv, 0.0) : zscale(sacc, 1.0 / piv);
+        __syncthreads();
+    }
+    if (tid == 0 && bad) notpd[s] = 1;
+}
+
+void launch_band_inertia(const int* list, int nt, const zd* zsite, const double* mu, const int64_t* cptr,
+                         const int64_t* ca, const int64_t* cb, const zd* vC, int64_t n, int b, zd* W,
+                         int64_t wstride, double floor_rel, int* notpd, hipStream_t s)
+{
+    if (nt <= 0) return;
+    hipLaunchKernelGGL(k_band_inertia, dim3(nt), dim3(64), 0, s, list, zsite, mu, cptr, ca, cb, vC, n, b, W, wstride,
+                       floor_rel, notpd);
 }

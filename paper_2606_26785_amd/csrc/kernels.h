@@ -221,6 +221,11 @@ struct SparsePattern {
 // sites (notpd[site] set on a non-positive pivot)
 void launch_icn(const int* list, int ns, const SparsePattern& sp, const zd* vC, const zd* zsite, const double* alpha,
                 zd* lu, int* notpd, hipStream_t s);
+// inertia tests of N(z_s) - mu_s I for a narrow-band N (bandwidth b <= 63):
+// notpd[s] set when the band Cholesky meets a pivot <= floor_rel
+void launch_band_inertia(const int* list, int nt, const zd* zsite, const double* mu, const int64_t* cptr,
+                         const int64_t* ca, const int64_t* cb, const zd* vC, int64_t n, int b, zd* W,
+                         int64_t wstride, double floor_rel, int* notpd, hipStream_t s);
 // Y = F^{-1} X (trans 0) or F^{-*} X (trans 1), K = F^* F the incomplete
 // Cholesky factorization of each item's site
 void launch_ic_solve(const int* list, int ni, const int* site, const SparsePattern& sp, const zd* lu, int trans,

@@ -446,6 +446,26 @@ extern "C" ps_status ps_debug_sparse_site(ps_matrix* h, double z_re, double z_im
     }
 }
 
+// One inertia test: is N(z) - mu I positive definite?
+extern "C" ps_status ps_debug_inertia(ps_matrix* h, double z_re, double z_im, double mu, int32_t* pd)
+{
+    if (!h || !pd) return fail(PS_EINVAL, "NULL argument");
+    try {
+        Engine& E = h->eng;
+        if (!E.use_prec) return fail(PS_EUNSUPPORTED, "no preconditioner on this handle");
+        if (E.op.kind != PS_DENSE && E.band_b < 0) return fail(PS_EUNSUPPORTED, "N(z) has no narrow band");
+        if (E.T < 1 || E.NS < 1) E.size_for(std::max(E.T, 1));
+        std::vector<double> mus = {mu};
+        std::vector<char> p;
+        E.build_precond({zmake(z_re, z_im)}, &mus, &p, true, true);
+        HIPCHK(hipStreamSynchronize(E.st));
+        *pd = p.empty() ? 0 : p[0];
+        return PS_OK;
+    } catch (const std::exception& e) {
+        return fail(PS_EDEVICE, e.what());
+    }
+}
+
 // The recycled singular store of one tile as the last ps_eval left it.
 extern "C" ps_status ps_debug_store(ps_matrix* h, int32_t tile, int32_t* k, double* V, double* W1, double* W3,
                                     double* W4, double* RA, double* Rres)
