@@ -426,6 +426,7 @@ ps_status Engine::eval(const ps_gridh* g, const double* eps, int n_eps, double* 
                     ra.mode = 0;
                     ra.eta = P.eta;
                     ra.floor_c = std::max(16.0, 4.0 * sqrt((double)n));
+                    ra.floor_tol = P.tol_abs * nC;
                     ra.eta_abs = P.eta_abs;
                     ra.normC = nC;
                     ra.xi = j_xi.p;

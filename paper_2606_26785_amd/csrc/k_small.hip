@@ -320,8 +320,13 @@ __global__ void __launch_bounds__(NT) k_ritz(RitzArgs a)
         int acc = 1;
         if (a.mode == 0) {
             double xi0 = sv[perm[0]];
-            double thr = fmax(a.eta * xi0 * nrm, a.floor_c * nrm * nrm * 2.220446049250313e-16);
-            acc = (sres[0] <= thr) || (xi0 <= a.eta_abs * a.normC);
+            // a residual w of the Hermitian N(z) puts some sigma_j^2 within w of
+            // xi0^2, so |sigma_j - xi0| <= w / xi0: the floor alone decides only
+            // where that bound is within floor_tol
+            const bool lin = sres[0] <= a.eta * xi0 * nrm;
+            const bool flo = sres[0] <= a.floor_c * nrm * nrm * 2.220446049250313e-16 &&
+                             (a.floor_tol <= 0.0 || sres[0] <= a.floor_tol * xi0);
+            acc = lin || flo || (xi0 <= a.eta_abs * a.normC);
         } else {
             for (int v = 0; v < nv; ++v) acc &= (sres[v] <= a.eta * nrm);
         }

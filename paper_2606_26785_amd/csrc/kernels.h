@@ -16,6 +16,8 @@ struct RitzArgs {
     int nv, ng, max_sweeps, mode;
     double eta;
     double floor_c;        // floor of tolC: floor_c * eps * nrm^2
+    double floor_tol;      // a residual accepted on the floor alone must also be
+                           // <= floor_tol * xi_0 (0: no such test)
     double eta_abs;        // accept when xi_0 <= eta_abs * normC (upper-bound certificate)
     double normC;
     double* xi; double* res; int ldxi;     // per job nv values
