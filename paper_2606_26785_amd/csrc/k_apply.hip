@@ -213,6 +213,16 @@ void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s)
 // TBN = 32: four waves, each 16 rows x 32 columns of the 64 x 32 tile
 // (2 MFMA blocks); TBN = 64: a 2 x 2 wave grid, each 32 x 32 of the 64 x 64
 // tile (2 x 2 MFMA blocks, half the LDS reads and global bytes per flop).
+// v where keep holds, +0 otherwise, by a bit mask: a select on the value
+// would let the compiler turn the staging into a load through a selected
+// private-memory address
+__device__ __forceinline__ zd zkeep(zd v, bool keep)
+{
+    const unsigned long long m = keep ? ~0ull : 0ull;
+    return zmake(__longlong_as_double(__double_as_longlong(v.x) & m),
+                 __longlong_as_double(__double_as_longlong(v.y) & m));
+}
+
 template <int TBN, int TBK>
 __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
 {
@@ -251,7 +261,7 @@ __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
         int64_t gj = j0 + tid / TBK + (NT / TBK) * q;
-        bcol[q] = nullptr;
+        bcol[q] = B;
         if (gj < Nb) bcol[q] = gt ? B + (size_t)gt[gj / a.cw] * a.strideB + (gj % a.cw) * a.ldb : B + gj * a.ldb;
     }
     dvec4 acc_re[RB][2], acc_im[RB][2];
@@ -266,40 +276,38 @@ __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
     // software pipeline: the next K tile is loaded into registers while the
     // matrix cores work on the current one from LDS
     constexpr int AQ = BM * TBK / NT;
+    // every load is issued unconditionally (an element outside the operand
+    // reads the operand's first element instead) and masked when staged
+    // into LDS: a conditional load would have to complete before the
+    // matrix-core work of the current tile, which defeats the prefetch
     zd ra[AQ], rb_[BQ];
+    auto a_ok = [&](int q, int64_t kt) {
+        if (a.opA == 0) return i0 + tid % BM < a.M && kt + tid / BM + (NT / BM) * q < kend;
+        return i0 + tid / TBK + (NT / TBK) * q < a.M && kt + tid % TBK < kend;
+    };
+    auto b_ok = [&](int q, int64_t kt) { return j0 + tid / TBK + (NT / TBK) * q < Nb && kt + tid % TBK < kend; };
     auto gload = [&](int64_t kt) {
-        if (a.opA == 0) {
-            const int64_t gi = i0 + tid % BM;
 #pragma unroll
-            for (int q = 0; q < AQ; ++q) {
-                const int64_t gk = kt + tid / BM + (NT / BM) * q;
-                ra[q] = (gi < a.M && gk < kend) ? A[gi + gk * a.lda] : zmake(0.0, 0.0);
-            }
-        } else {
-            const int64_t gk = kt + tid % TBK;
-#pragma unroll
-            for (int q = 0; q < AQ; ++q) {
-                const int64_t gi = i0 + tid / TBK + (NT / TBK) * q;
-                ra[q] = (gi < a.M && gk < kend) ? zconj(A[gk + gi * a.lda]) : zmake(0.0, 0.0);
-            }
+        for (int q = 0; q < AQ; ++q) {
+            const int64_t idx = (a.opA == 0) ? (i0 + tid % BM) + (kt + tid / BM + (NT / BM) * q) * a.lda
+                                             : (kt + tid % TBK) + (i0 + tid / TBK + (NT / TBK) * q) * a.lda;
+            ra[q] = A[a_ok(q, kt) ? idx : 0];
         }
 #pragma unroll
-        for (int q = 0; q < BQ; ++q) {
-            const int64_t gk = kt + tid % TBK;
-            rb_[q] = (bcol[q] && gk < kend) ? bcol[q][gk] : zmake(0.0, 0.0);
-        }
+        for (int q = 0; q < BQ; ++q) rb_[q] = bcol[q][b_ok(q, kt) ? kt + tid % TBK : 0];
     };
     if (kbeg < kend) gload(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += TBK) {
         if (a.opA == 0) {
 #pragma unroll
-            for (int q = 0; q < AQ; ++q) As[tid / BM + (NT / BM) * q][tid % BM] = ra[q];
+            for (int q = 0; q < AQ; ++q) As[tid / BM + (NT / BM) * q][tid % BM] = zkeep(ra[q], a_ok(q, k0));
         } else {
 #pragma unroll
-            for (int q = 0; q < AQ; ++q) As[tid % TBK][tid / TBK + (NT / TBK) * q] = ra[q];
+            for (int q = 0; q < AQ; ++q)
+                As[tid % TBK][tid / TBK + (NT / TBK) * q] = zkeep(zconj(ra[q]), a_ok(q, k0));
         }
 #pragma unroll
-        for (int q = 0; q < BQ; ++q) Bs[tid % TBK][tid / TBK + (NT / TBK) * q] = rb_[q];
+        for (int q = 0; q < BQ; ++q) Bs[tid % TBK][tid / TBK + (NT / TBK) * q] = zkeep(rb_[q], b_ok(q, k0));
         __syncthreads();
         if (k0 + TBK < kend) gload(k0 + TBK);
 #pragma unroll
