@@ -61,15 +61,35 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
     if (chunk > 0 && cbeg >= n) return;
     zd* Ab = A + (size_t)tile * strideA;
     if (tid == 0) bad = 0;
-    for (int e = tid; e < kb * kb; e += NT) {
-        int i = e % kb, j = e / kb;
-        R[i][j] = (i <= j) ? Ab[k0 + i + (k0 + j) * n] : zmake(0.0, 0.0);
+    // entries outside the kb x kb block hold the identity, so that the
+    // register back substitution below runs over all 32 rows unguarded
+    for (int e = tid; e < 32 * 32; e += NT) {
+        const int i = e & 31, j = e >> 5;
+        if (i < kb && j < kb) R[i][j] = (i <= j) ? Ab[k0 + i + (k0 + j) * n] : zmake(0.0, 0.0);
+        else R[i][j] = zmake(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
     // right-looking factorization with one barrier per pivot: in phase j the
     // trailing rows a > j are updated from the unscaled row j
     // (R[a][c] -= conj(R[j][a]) R[j][c] / d_j), and row j - 1, which nothing
     // reads any more, is scaled by 1 / sqrt(d_{j-1})
+    // each thread owns up to three entries (a2 <= c) of the upper triangle
+    int ua[3], uc[3];
+    const int ntri = kb * (kb + 1) / 2;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int u = tid + NT * q, a2 = 0;
+        ua[q] = -1;
+        uc[q] = 0;
+        if (u < ntri) {
+            while (u >= kb - a2) {
+                u -= kb - a2;
+                ++a2;
+            }
+            ua[q] = a2;
+            uc[q] = a2 + u;
+        }
+    }
     double pprev = 1.0;
     for (int j = 0; j <= kb; ++j) {
         double pj = 1.0, ipj2 = 1.0;
@@ -80,10 +100,12 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
             pj = sqrt(d);
             ipj2 = 1.0 / d;
         }
-        for (int e = tid; e < kb * kb; e += NT) {
-            const int a2 = e % kb, c = e / kb;
-            if (j < kb && a2 > j && c >= a2) R[a2][c] = zsub(R[a2][c], zscale(zcmul(R[j][a2], R[j][c]), ipj2));
-            if (j > 0 && a2 == j - 1 && c >= a2) R[a2][c] = (c == a2) ? zmake(pprev, 0.0) : zscale(R[a2][c], 1.0 / pprev);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int a2 = ua[q], c = uc[q];
+            if (a2 < 0) continue;
+            if (j < kb && a2 > j) R[a2][c] = zsub(R[a2][c], zscale(zcmul(R[j][a2], R[j][c]), ipj2));
+            if (j > 0 && a2 == j - 1) R[a2][c] = (c == a2) ? zmake(pprev, 0.0) : zscale(R[a2][c], 1.0 / pprev);
         }
         pprev = pj;
         __syncthreads();
@@ -93,14 +115,22 @@ __global__ void __launch_bounds__(NT) k_chol_step(const int* list, zd* A, int64_
         zd* Db = Dinv ? Dinv + (size_t)tile * strideD + k0 : nullptr;
         zd* Fb = Finv ? Finv + (size_t)tile * strideF + k0 + k0 * n : nullptr;
         if (!Db && !Fb) return;
-        // X = R^{-1} (upper), one thread per column
-        for (int c = tid; c < kb; c += NT) {
-            for (int i = kb - 1; i >= 0; --i) {
-                if (i > c) { X[i][c] = zmake(0.0, 0.0); continue; }
-                zd s = zmake(i == c ? 1.0 : 0.0, 0.0);
-                for (int l = i + 1; l <= c; ++l) s = zsub(s, zmul(R[i][l], X[l][c]));
-                X[i][c] = zscale(s, 1.0 / R[i][i].x);
+        // X = R^{-1} (upper) by back substitution, column c held in the
+        // registers of thread c; rows below c come out zero, since x[l] = 0
+        // for l > c throughout
+        if (tid < kb) {
+            const int c = tid;
+            zd x[32];
+#pragma unroll
+            for (int i = 31; i >= 0; --i) {
+                zd sacc = zmake(i == c ? 1.0 : 0.0, 0.0);
+#pragma unroll
+                for (int l = i + 1; l < 32; ++l) sacc = zsub(sacc, zmul(R[i][l], x[l]));
+                x[i] = zscale(sacc, 1.0 / R[i][i].x);
             }
+#pragma unroll
+            for (int i = 0; i < 32; ++i)
+                if (i < kb) X[i][c] = x[i];
         }
         __syncthreads();
         // (R_kk is not written back: the other workgroups of this launch
