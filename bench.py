@@ -43,7 +43,7 @@ CLASS_NAMES = ["operator_apply", "precond_apply", "ritz_extraction", "factorizat
                "factorization_diag", "small_per_tile", "tall_skinny", "other", "factorization_gemm_narrow"]
 CLASS_BOUND = ["mfma", "mfma", "alu", "mfma", "alu", "alu", "hbm", "hbm", "mfma"]
 CLASS_KERNELS = ["k_dense_gemm + k_dense_reduce (dense) or k_csr_apply (CSR)", "k_zgemm (+ k_zgemm_reduce)",
-                 "k_ritz", "k_zgemm_fact64", "k_chol_step, k_form_normal",
+                 "k_ritz", "k_zgemm_fact_wide", "k_chol_step, k_form_normal",
                  "k_rr_hl, k_chol_dd, k_svqb, k_rotations", "k_gram_part, k_gemm_ts, k_colnorm_part",
                  "copies, fills", "k_zgemm_fact (+ k_zgemm_reduce)"]
 
@@ -73,8 +73,8 @@ def measured_traffic(kernel):
         return None
     t = float(fields["traffic_bytes_per_launch"])
     a = float(fields["algorithmic_bytes_per_launch"])
-    return {"bytes_per_launch": t, "over_algorithmic": t / a, "workload": fields.get("workload"),
-            "source": "profiles/%s_traffic.md" % kernel}
+    return {"counted_bytes_per_launch": t, "counted_algorithmic_bytes_per_launch": a, "over_algorithmic": t / a,
+            "counted_workload": fields.get("workload"), "source": "profiles/%s_traffic.md" % kernel}
 
 
 def path_work(st, n, r, k):
@@ -248,7 +248,10 @@ def main():
             achieved, peak, unit = fl / (avg_ms * 1e-3) / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
         tr = measured_traffic(CLASS_KERNELS[c]) if " " not in CLASS_KERNELS[c] else None
         roofline = {"bound": CLASS_BOUND[c], "achieved": achieved, "peak": peak, "unit": unit,
-                    "frac": achieved / peak, "traffic": tr["bytes_per_launch"] if tr else None,
+                    "frac": achieved / peak,
+                    # measured traffic / algorithmic bytes of the counted run, applied to
+                    # this run's algorithmic bytes per launch
+                    "traffic": tr["over_algorithmic"] * by if tr else None,
                     "traffic_detail": tr, "kernel_class": CLASS_NAMES[c], "kernels": CLASS_KERNELS[c],
                     "launches": int(launches), "avg_launch_ms": avg_ms, "flops_per_launch": fl,
                     "bytes_per_launch": by,

@@ -57,7 +57,7 @@ void Engine::zgemm(const int* dl, int nt, int64_t M, int64_t N, int64_t Kd, cons
     double fl = 8.0 * (double)M * ncols * Kd * ((upper || tri) ? 0.5 : 1.0);
     double by = 16.0 * ((double)nt * M * Kd * (tri ? 0.5 : 1.0) + (double)Kd * ncols +
                         (double)M * ncols * (beta != 0.0 ? 2.0 : 1.0));
-    // inside factorizations: class 3 for the 64 x 64-tile kernel (products
+    // inside factorizations: class 3 for the wide-product kernel (products
     // at least 64 columns wide), 8 for the narrower ones
     const int cls = (zgemm_cls == 3 && (gmap || N < 64)) ? 8 : zgemm_cls;
     int pi = prof.begin(st, cls, fl, by);

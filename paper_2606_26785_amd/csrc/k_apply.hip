@@ -210,9 +210,8 @@ void launch_csr_apply(const CsrApplyArgs& a, hipStream_t s)
 // computed (Hermitian rank-k updates).  The K loop of a workgroup finishes
 // before its epilogue writes, so C may alias B when M <= 64 (in-place
 // left-multiplication of a panel by a small matrix).
-// TBN = 32: four waves, each 16 rows x 32 columns of the 64 x 32 tile
-// (2 MFMA blocks); TBN = 64: a 2 x 2 wave grid, each 32 x 32 of the 64 x 64
-// tile (2 x 2 MFMA blocks, half the LDS reads and global bytes per flop).
+// Four waves, each 16 rows x 32 columns of the 64 x 32 tile (2 MFMA
+// blocks); TBK is the K step staged through LDS.
 // v where keep holds, +0 otherwise, by a bit mask: a select on the value
 // would let the compiler turn the staging into a load through a selected
 // private-memory address
@@ -223,16 +222,17 @@ __device__ __forceinline__ zd zkeep(zd v, bool keep)
                  __longlong_as_double(__double_as_longlong(v.y) & m));
 }
 
-template <int TBN, int TBK>
+template <int TBK>
 __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
 {
-    constexpr int RB = (TBN == 32) ? 1 : 2;   // 16-row blocks per wave
+    constexpr int TBN = BN;
+    constexpr int RB = 1;   // 16-row blocks per wave
     __shared__ zd As[TBK][BM + 1];
     __shared__ zd Bs[TBK][TBN + 1];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int wr0 = (TBN == 32) ? wave * 16 : (wave & 1) * 32;   // wave's first row in the tile
-    const int wc0 = (TBN == 32) ? 0 : (wave >> 1) * 32;          // wave's first column
+    const int wr0 = wave * 16;   // wave's first row in the tile
+    const int wc0 = 0;           // wave's first column
     const int64_t i0 = (int64_t)blockIdx.x * BM;
     const int64_t j0 = (int64_t)blockIdx.y * TBN;
     const int nb = gridDim.z / a.splitk;
@@ -358,12 +358,16 @@ __device__ __forceinline__ void k_zgemm_body(const ZgemmArgs& a)
     }
 }
 
-// k_zgemm: preconditioner applies and small products; k_zgemm_fact and
-// k_zgemm_fact64: products inside factorizations (64 x 32 and 64 x 64
-// tiles), under their own names so that profiles separate them
-__global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a) { k_zgemm_body<32, BK>(a); }
-__global__ void __launch_bounds__(NT) k_zgemm_fact(ZgemmArgs a) { k_zgemm_body<32, BK>(a); }
-__global__ void __launch_bounds__(NT) k_zgemm_fact64(ZgemmArgs a) { k_zgemm_body<64, 16>(a); }
+// k_zgemm: preconditioner applies and small products; k_zgemm_fact_wide and
+// k_zgemm_fact: products inside factorizations at least 64 columns wide and
+// narrower ones, under their own names so that profiles separate them.  The
+// factorization products take 64 x 32 tiles with a K step of 16: on the
+// Hermitian trailing updates of order 400 to 3,900 (rank 128) these ran at
+// 1.15 to 1.7 times the rate of 64 x 64 tiles and ahead of K steps of 8, 32
+// and 64
+__global__ void __launch_bounds__(NT) k_zgemm(ZgemmArgs a) { k_zgemm_body<BK>(a); }
+__global__ void __launch_bounds__(NT) k_zgemm_fact(ZgemmArgs a) { k_zgemm_body<16>(a); }
+__global__ void __launch_bounds__(NT) k_zgemm_fact_wide(ZgemmArgs a) { k_zgemm_body<16>(a); }
 
 // sum of the split-K partials into C (alpha, beta as in k_zgemm)
 __global__ void __launch_bounds__(NT) k_zgemm_reduce(ZgemmArgs a, int nb)
@@ -392,11 +396,10 @@ void launch_zgemm(const ZgemmArgs& a, int nbatch, hipStream_t s, int fact)
 {
     if (nbatch <= 0 || a.M <= 0 || a.N <= 0) return;
     const int sk = a.splitk > 1 ? a.splitk : 1;
-    // factorization products at least 64 columns wide: 64 x 64 tiles
-    const bool t64 = (fact == 2) && !a.gtile && a.N >= 64;
-    const int tbn = t64 ? 64 : BN;
-    dim3 g((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + tbn - 1) / tbn), nbatch * sk);
-    if (t64) hipLaunchKernelGGL(k_zgemm_fact64, g, dim3(NT), 0, s, a);
+    // factorization products at least 64 columns wide under their own name
+    const bool wide = (fact == 2) && !a.gtile && a.N >= 64;
+    dim3 g((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + BN - 1) / BN), nbatch * sk);
+    if (wide) hipLaunchKernelGGL(k_zgemm_fact_wide, g, dim3(NT), 0, s, a);
     else if (fact) hipLaunchKernelGGL(k_zgemm_fact, g, dim3(NT), 0, s, a);
     else hipLaunchKernelGGL(k_zgemm, g, dim3(NT), 0, s, a);
     if (sk > 1) {
