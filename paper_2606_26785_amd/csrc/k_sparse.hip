@@ -122,17 +122,21 @@ __global__ void k_sptrsv_color(SpSolveArgs a)
     const int64_t i = a.r0 + g;
     const zd* v = a.lu + (size_t)s * a.nnz;
     zd* x = a.X + (size_t)item * a.xs + (size_t)c0 * a.ldx;
+    // every column's load unguarded, so that they are in flight together:
+    // the columns past nc repeat column c0, and their results are dropped
+    size_t cof[TRSV_CW];
+#pragma unroll
+    for (int k = 0; k < TRSV_CW; ++k) cof[k] = (size_t)(k < nc ? k : 0) * a.ldx;
     zd acc[TRSV_CW];
 #pragma unroll
-    for (int k = 0; k < TRSV_CW; ++k) acc[k] = (k < nc) ? x[i + (size_t)k * a.ldx] : zmake(0.0, 0.0);
+    for (int k = 0; k < TRSV_CW; ++k) acc[k] = x[i + cof[k]];
     for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
         const int32_t j = a.ci[p];
         if (a.part == 0 ? j >= i : j <= i) continue;
         zd val = v[a.map ? a.map[p] : p];
         if (a.conj) val = zconj(val);
 #pragma unroll
-        for (int k = 0; k < TRSV_CW; ++k)
-            if (k < nc) acc[k] = zsub(acc[k], zmul(val, x[j + (size_t)k * a.ldx]));
+        for (int k = 0; k < TRSV_CW; ++k) acc[k] = zsub(acc[k], zmul(val, x[j + cof[k]]));
     }
 #pragma unroll
     for (int k = 0; k < TRSV_CW; ++k)

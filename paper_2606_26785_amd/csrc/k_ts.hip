@@ -41,6 +41,18 @@ __device__ inline int bl_total(const BlockList& L, int t)
     return s;
 }
 
+// v where keep holds, +0 otherwise, by a bit mask. The Gram staging below loads
+// from a clamped in-bounds address unconditionally and masks the value: a
+// conditional load must complete before the code after it, which keeps the
+// next loads from being issued early, and a select on the loaded value can
+// be turned into a load through a selected private-memory address
+__device__ __forceinline__ zd zkeep(zd v, bool keep)
+{
+    const unsigned long long m = keep ? ~0ull : 0ull;
+    return zmake(__longlong_as_double(__double_as_longlong(v.x) & m),
+                 __longlong_as_double(__double_as_longlong(v.y) & m));
+}
+
 // ---------------------------------------------------------------------------
 // Gram: part[(tile, chunk)] = A[rows of chunk]^* B[rows of chunk] for one
 // CA x CB output tile per workgroup (grid: chunks x out-tiles x tiles), CA and
@@ -57,9 +69,6 @@ __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
     constexpr int SR = 32;                       // rows per staging step
     __shared__ zd As[SR][CA + 1];
     __shared__ zd Bs[SR][CB + 1];
-    __shared__ const zd* pa[CA];
-    __shared__ const zd* pb[CB];
-    __shared__ int64_t na[CA], nb_[CB];
     const int chunk = blockIdx.x;
     const int ot = blockIdx.y;
     const int ti = ot / ntj, tj = ot % ntj;
@@ -72,17 +81,29 @@ __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
     const int64_t r0 = (int64_t)chunk * a.chunk_rows;
     int64_t r1 = r0 + a.chunk_rows;
     if (r1 > a.A.rows) r1 = a.A.rows;
-    // the CA + CB columns of this output tile, resolved once
-    if (tid < CA) {
-        const int g = ti * CA + tid;
-        pa[tid] = (g < ca) ? bl_col(a.A, tile, g, na[tid]) : nullptr;
-        if (g >= ca) na[tid] = 0;
-    } else if (tid < CA + CB) {
-        const int c = tid - CA, g = tj * CB + c;
-        pb[c] = (g < cb) ? bl_col(a.B, tile, g, nb_[c]) : nullptr;
-        if (g >= cb) nb_[c] = 0;
+    // the columns this thread stages, resolved once into registers (held in
+    // LDS, the pointers would lose their address space and every staging
+    // load would become a flat load that LDS waits also wait for); a column
+    // past the operand's last points at its first column with no rows, so
+    // that the staging loads below always have a valid address
+    constexpr int QA = (SR * CA + NT - 1) / NT, QB = (SR * CB + NT - 1) / NT;
+    const zd* pa[QA];
+    const zd* pb[QB];
+    int64_t na[QA], nb_[QB];
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+        const int g = ti * CA + ((tid + NT * q) / SR) % CA;
+        int64_t nr = 0;
+        pa[q] = bl_col(a.A, tile, g < ca ? g : 0, nr);
+        na[q] = (g < ca) ? nr : 0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        const int g = tj * CB + ((tid + NT * q) / SR) % CB;
+        int64_t nr = 0;
+        pb[q] = bl_col(a.B, tile, g < cb ? g : 0, nr);
+        nb_[q] = (g < cb) ? nr : 0;
+    }
     int oi[Q], oj[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -98,15 +119,31 @@ __global__ void __launch_bounds__(NT) k_gram_part(GramArgs a, int ntj)
     for (int64_t rb = r0; rb < r1; rb += SR) {
         // stage SR rows of the CA + CB columns (consecutive threads take
         // consecutive rows of one column)
-        for (int e = tid; e < SR * CA; e += NT) {
-            const int rr = e % SR, cc = e / SR;
-            const int64_t i = rb + rr;
-            As[rr][cc] = (i < r1 && i < na[cc]) ? pa[cc][i] : zmake(0.0, 0.0);
+        zd va[QA], vb[QB];
+        bool ka[QA], kb[QB];
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q;
+            const int64_t i = rb + e % SR;
+            ka[q] = e < SR * CA && i < r1 && i < na[q];
+            va[q] = pa[q][ka[q] ? i : 0];
         }
-        for (int e = tid; e < SR * CB; e += NT) {
-            const int rr = e % SR, cc = e / SR;
-            const int64_t i = rb + rr;
-            Bs[rr][cc] = (i < r1 && i < nb_[cc]) ? pb[cc][i] : zmake(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + NT * q;
+            const int64_t i = rb + e % SR;
+            kb[q] = e < SR * CB && i < r1 && i < nb_[q];
+            vb[q] = pb[q][kb[q] ? i : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q;
+            if (e < SR * CA) As[e % SR][e / SR] = zkeep(va[q], ka[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + NT * q;
+            if (e < SR * CB) Bs[e % SR][e / SR] = zkeep(vb[q], kb[q]);
         }
         __syncthreads();
         const int nr = (int)((r1 - rb) < SR ? (r1 - rb) : SR);
@@ -258,8 +295,24 @@ __global__ void __launch_bounds__(NT) k_gemm_ts(GemmTSArgs a)
             const int tb = bl_t(a.A, b, tile);
             int cof = a.A.coff[b] ? a.A.coff[b][tb] * a.A.coffmul[b] : 0;
             const zd* p = a.A.ptr[b] + (size_t)tb * a.A.stride[b] + (size_t)cof * a.A.ld[b] + row;
-            for (int c = 0; c < ncb; ++c) {
-                zd x = p[(size_t)c * a.A.ld[b]];
+            const int64_t ld = a.A.ld[b];
+            int c = 0;
+            // four columns' loads in flight at once; per output column the
+            // products are still added in column order
+            for (; c + 4 <= ncb; c += 4) {
+                const zd x0 = p[(size_t)c * ld], x1 = p[(size_t)(c + 1) * ld];
+                const zd x2 = p[(size_t)(c + 2) * ld], x3 = p[(size_t)(c + 3) * ld];
+                const zd* gr = Gs + (cglob + c);
+#pragma unroll
+                for (int j = 0; j < TSC; ++j) {
+                    zfma(acc[j], x0, gr[j * ca]);
+                    zfma(acc[j], x1, gr[j * ca + 1]);
+                    zfma(acc[j], x2, gr[j * ca + 2]);
+                    zfma(acc[j], x3, gr[j * ca + 3]);
+                }
+            }
+            for (; c < ncb; ++c) {
+                const zd x = p[(size_t)c * ld];
                 const zd* gr = Gs + (cglob + c);
 #pragma unroll
                 for (int j = 0; j < TSC; ++j) zfma(acc[j], x, gr[j * ca]);
@@ -268,11 +321,18 @@ __global__ void __launch_bounds__(NT) k_gemm_ts(GemmTSArgs a)
         cglob += ncb;
     }
     zd* Y = a.Y + (size_t)tile * a.strideY + row;
+    // the old values are all read before the first store (column c0 stands
+    // in for the columns past nc)
+    zd yo[TSC];
+    if (a.beta != 0.0) {
+#pragma unroll
+        for (int j = 0; j < TSC; ++j) yo[j] = Y[(size_t)(c0 + (j < nc ? j : 0)) * a.ldY];
+    }
 #pragma unroll
     for (int j = 0; j < TSC; ++j) {
         if (j < nc) {
             zd v = zscale(acc[j], a.alpha);
-            if (a.beta != 0.0) v = zadd(v, Y[(size_t)(c0 + j) * a.ldY]);
+            if (a.beta != 0.0) v = zadd(v, yo[j]);
             Y[(size_t)(c0 + j) * a.ldY] = v;
         }
     }
@@ -303,7 +363,16 @@ __global__ void __launch_bounds__(NT) k_colnorm_part(NormArgs a)
         int64_t nr = 0;
         const zd* col = bl_col(a.A, tile, c, nr);
         const int64_t re = r1 < nr ? r1 : nr;
-        for (int64_t i = r0 + lane; i < re; i += 64) s += zabs2(col[i]);
+        int64_t i = r0 + lane;
+        // four loads in flight at once; the sum keeps the row order
+        for (; i + 192 < re; i += 256) {
+            const zd v0 = col[i], v1 = col[i + 64], v2 = col[i + 128], v3 = col[i + 192];
+            s += zabs2(v0);
+            s += zabs2(v1);
+            s += zabs2(v2);
+            s += zabs2(v3);
+        }
+        for (; i < re; i += 64) s += zabs2(col[i]);
         s = wave_sum(s);
         if (lane == 0) a.part[((size_t)tix * a.nchunks + chunk) * a.camax + c] = s;
     }
