@@ -163,11 +163,15 @@ typedef struct {
                            after esc_iters iterations is accepted when
                            N(z) - mu I, mu = (xi - tau)^2 + rounding slack, is
                            positive definite (then xi - tau <= sigma_min <= xi);
-                           0 disables (dense C with precond = 1 only) */
+                           0 disables.  The test factors N(z) - mu I exactly:
+                           dense C, and CSR C whose N has bandwidth <= 63
+                           in the natural order (a band Cholesky); other CSR
+                           matrices get no certificate */
     int32_t esc_iters;  /* escalation period of slow refinements: the
-                           inertia test above, a shifted preconditioner
-                           N(z) - (xi - 64 tau)^2 I, or an exact site at z
-                           (default 30; 0 disables) */
+                           inertia test above, then (dense C) a shifted
+                           preconditioner N(z) - (xi - 64 tau)^2 I, else
+                           N(z) - (xi - 4096 tau)^2 I, else an exact site at
+                           z (default 30; 0 disables) */
     int32_t cert_recycled; /* 1: in a cluster regime, test a recycled Ritz
                            value that failed eq. (tolC) with the inertia test
                            before starting LOBPCG (default 0: on the dense
