@@ -42,5 +42,24 @@ def build(verbose=False):
     return OUT
 
 
+PEAKS_SRC = os.path.join(HERE, "peaks.hip")
+PEAKS_BIN = os.path.join(HERE, "peaks")
+
+
+def build_peaks(verbose=False):
+    """Compile the peak probes (peaks.hip: copy, FP64 FMA and FP64 MFMA
+    loops) into the executable paper_2606_26785_amd/peaks."""
+    tmp = PEAKS_BIN + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + [PEAKS_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (PEAKS_SRC, r.stderr))
+    os.replace(tmp, PEAKS_BIN)
+    if verbose:
+        print("built", PEAKS_BIN)
+    return PEAKS_BIN
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_peaks(verbose=True)
