@@ -48,6 +48,23 @@ CLASS_KERNELS = ["k_dense_gemm + k_dense_reduce (dense) or k_csr_apply (CSR)", "
                  "copies, fills", "k_zgemm_fact (+ k_zgemm_reduce)"]
 
 
+# The paper's own timings (Sec. 4, Tables 1 and 2), for context only: other
+# matrices (its dense examples are basor, a Toeplitz matrix of n = 2,000, and
+# landau_40pi, n = 5,000), no stated accuracy bar, and other hardware (Julia,
+# one thread of a 2.90 GHz Intel Core i5); 200 x 200 grids throughout.
+PAPER_CONTEXT = {
+    "hardware": "Julia v1.12, single thread, 2.90 GHz Intel Core i5, 16 GB",
+    "grid_points": 40000,
+    "dense": [
+        {"matrix": "basor", "n": 2000, "psTriRecy_s": 1352, "psTriRecy_pts_per_s": 40000 / 1352,
+         "psInvLanc_s": 7251, "psInvLanc_pts_per_s": 40000 / 7251},
+        {"matrix": "landau_40pi", "n": 5000, "psTriRecy_s": 2006, "psTriRecy_pts_per_s": 40000 / 2006,
+         "psInvLanc_s": 9069, "psInvLanc_pts_per_s": 40000 / 9069},
+    ],
+    "note": "different matrices, accuracy and hardware: context, not a baseline for this workload",
+}
+
+
 def measured_traffic(kernel):
     """The HBM traffic per launch of `kernel` stored in profiles/<kernel>_traffic.md
     (rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by a copy of known
@@ -398,6 +415,7 @@ def main():
         "roofline": roofline,
         "roofline_path": roofline_path,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT if wl.kind == "dense" else None,
     }
     print(json.dumps(out), flush=True)
     mat.close()

@@ -61,3 +61,16 @@ def test_committed_traffic_profile_is_readable():
     assert os.path.exists(os.path.join(ROOT, fields["kernel_source"]))
     assert float(fields["traffic_bytes_per_launch"]) > float(fields["algorithmic_bytes_per_launch"]) > 0
     assert "k_zgemm_fact_wide" in bench.CLASS_KERNELS
+
+
+def test_paper_context_is_the_published_table():
+    """The context block of the bench line restates the paper's Table 2 times
+    for its dense examples (40,000 grid points each) and serialises to JSON."""
+    import json
+    bench = _bench_module()
+    ctx = json.loads(json.dumps(bench.PAPER_CONTEXT))
+    rows = {r["matrix"]: r for r in ctx["dense"]}
+    assert rows["basor"]["psTriRecy_s"] == 1352 and rows["basor"]["psInvLanc_s"] == 7251
+    assert rows["landau_40pi"]["psTriRecy_s"] == 2006 and rows["landau_40pi"]["psInvLanc_s"] == 9069
+    for r in ctx["dense"]:
+        assert abs(r["psTriRecy_pts_per_s"] - ctx["grid_points"] / r["psTriRecy_s"]) < 1e-9
