@@ -194,8 +194,10 @@ def folding(seed: int, n: int, grid: int = 64, eps=EPS_6, bw: int = 4,
             name: str = "csr-folding") -> Workload:
     """Rectangular banded folding: m = n + bw rows, entry (row j, col k) =
     a_{j-k} for |j - k| <= bw, with the 2 bw + 1 Toeplitz constants
-    a_{-bw}..a_{bw} ~ CN(0,1) drawn in that order.  Every column is complete
-    (a truncation of an infinite banded matrix to its first n columns).
+    a_{-bw}..a_{bw} ~ CN(0,1) drawn in that order: the section of rows
+    0..n+bw-1 and columns 0..n-1 of the banded Toeplitz matrix, so that every
+    column from bw on holds its 2 bw + 1 entries and the first bw columns lose
+    the ones above row 0.
     Region: bounding box of the symbol curve sum_d a_d e^{i d theta},
     widened by 10% per axis.  Stored CSR."""
     rng = np.random.default_rng(seed)
