@@ -74,3 +74,27 @@ def test_paper_context_is_the_published_table():
     assert rows["landau_40pi"]["psTriRecy_s"] == 2006 and rows["landau_40pi"]["psInvLanc_s"] == 9069
     for r in ctx["dense"]:
         assert abs(r["psTriRecy_pts_per_s"] - ctx["grid_points"] / r["psTriRecy_s"]) < 1e-9
+
+
+def test_path_work_per_unit_figures():
+    """The per-unit algorithmic work bench.py charges, at the dense workload's
+    n = 4000, r = 8, k = 32: a Ritz test 8.2 MFLOP, a LOBPCG iteration two
+    operator products of 8 n^2 r flops each (2.05 GFLOP), a preconditioned
+    iteration 1.02 GFLOP more, a store update 3.07 GFLOP, an inertia test
+    8 n^3 / 3 and a site twice that."""
+    bench = _bench_module()
+    n, r, k = 4000, 8, 32
+    keys = ("ritz_jobs", "lobpcg_iters", "precond_iters", "store_updates", "cert_tests", "rebuilds")
+
+    def one(key):
+        st = {x: 0 for x in keys}
+        st[key] = 1
+        st["k_launches"] = [0] * 9
+        return bench.path_work(st, n, r, k)[0]
+
+    assert abs(one("ritz_jobs") - 8.192e6) < 1e3
+    assert abs(one("lobpcg_iters") - 2.048e9) < 1e3
+    assert abs(one("precond_iters") - 1.024e9) < 1e3
+    assert abs(one("store_updates") - 3.072e9) < 1e3
+    assert abs(one("cert_tests") - 8 * n ** 3 / 3) < 1e3
+    assert abs(one("rebuilds") - 16 * n ** 3 / 3) < 1e3
