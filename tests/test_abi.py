@@ -74,3 +74,30 @@ def test_default_params_without_gpu(lib):
     import paper_2606_26785_amd as P
     p = P.default_params()
     assert p.r == 8 and p.k_max == 32 and p.eta > 0 and p.lipschitz == 1
+
+
+def test_binding_struct_layout_matches_the_c_compiler(tmp_path):
+    """Field offsets and struct sizes of the binding's ctypes structures equal
+    what a C compiler lays out from include/ps.h (catches a field of the wrong
+    width, which the field order alone would not)."""
+    import subprocess
+    import paper_2606_26785_amd as P
+    structs = (("ps_params", P.ps_params), ("ps_stats", P.ps_stats), ("ps_matrix_desc", P.ps_matrix_desc))
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ps.h"', "int main(void) {"]
+    for cname, _ in structs:
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in _struct_fields(cname):
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", INC, str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, cls in structs:
+        assert ctypes.sizeof(cls) == got[(cname, "size")], cname
+        for f in _struct_fields(cname):
+            assert getattr(cls, f).offset == got[(cname, f)], (cname, f)
