@@ -101,3 +101,49 @@ def test_binding_struct_layout_matches_the_c_compiler(tmp_path):
         assert ctypes.sizeof(cls) == got[(cname, "size")], cname
         for f in _struct_fields(cname):
             assert getattr(cls, f).offset == got[(cname, f)], (cname, f)
+
+
+def _kind_c(param):
+    param = param.strip()
+    if "*" in param:
+        return "ptr"
+    if re.search(r"\bdouble\b", param):
+        return "f64"
+    if re.search(r"\bint64_t\b", param):
+        return "i64"
+    if re.search(r"\b(int32_t|int|ps_status|ps_kind)\b", param):
+        return "i32"
+    raise AssertionError("unclassified parameter: " + param)
+
+
+def _kind_ctypes(t):
+    if t in (ctypes.c_void_p, ctypes.c_char_p) or (isinstance(t, type) and issubclass(t, ctypes._Pointer)):
+        return "ptr"
+    if t is ctypes.c_double:
+        return "f64"
+    if t is ctypes.c_int64:
+        return "i64"
+    if t in (ctypes.c_int32, ctypes.c_int):
+        return "i32"
+    raise AssertionError("unclassified ctypes type: %r" % (t,))
+
+
+def test_binding_signatures_follow_the_headers(lib):
+    """Every function the binding declares has the parameter kinds and widths
+    of its prototype in include/*.h."""
+    import paper_2606_26785_amd as P
+    lib_b = P.load()
+    protos = {}
+    for h in _headers():
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for m in re.finditer(r"\b(ps_\w+)\s*\(([^)]*)\)\s*;", src):
+            params = [p for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+            protos[m.group(1)] = [_kind_c(p) for p in params]
+    checked = 0
+    for name, kinds in protos.items():
+        fn = getattr(lib_b, name)
+        if fn.argtypes is None:
+            continue
+        assert [_kind_ctypes(t) for t in fn.argtypes] == kinds, name
+        checked += 1
+    assert checked >= 15
